@@ -1,0 +1,220 @@
+"""Benchmark: time-to-solution at 1e-10 of MSPCG against plain FP64 CG on one GPU,
+plus dslash_eo bandwidth against the HBM roofline.
+
+One step = one full MSPCG solve (Algorithm 1, FP64 outer, low-precision batched
+block CG as preconditioner) of the normal equation from x = 0 to a true relative
+residual of 1e-10, on a seeded synthetic gauge field and source that are
+resident in HBM before timing starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1811_08488_amd import mspcg as M  # noqa: E402
+from paper_1811_08488_amd import synth  # noqa: E402
+from paper_1811_08488_amd.workloads import WORKLOADS  # noqa: E402
+
+METRIC = "time-to-solution @1e-10 MSPCG vs plain CG (s); dslash GB/s & % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+PREC = {"f32": M.F32, "f16": M.F16, "bf16": M.BF16, "f64": M.F64}
+BYTES = {M.F64: (8, 0), M.F32: (4, 0), M.F16: (2, 4), M.BF16: (2, 4)}
+
+
+def dslash_bytes_per_site(prec, Ls, nrhs):
+    """Algorithmic bytes per 5D output site: in + out spinor (+ norms) + links shared over Ls and rhs."""
+    w, n = BYTES[prec]
+    return 2 * (24 * w + n) + 144 * w / (Ls * nrhs)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def build_problem(w, torch):
+    eps = w.eps if w.eps is not None else synth.tuned_eps()
+    t0 = time.time()
+    U = synth.gauge_field(w.L, eps, w.gauge_seed)
+    phi = synth.source(w.L, w.Ls, w.nrhs, w.source_seed)
+    log(f"[bench] inputs generated in {time.time() - t0:.1f}s (eps={eps:.4f})")
+    A = M.Action(w.L, w.Ls, M5=w.M5, mf=w.mf, b=w.b, c=w.c, t_bc=-1)
+    h = M.Handle(A, U)
+    # split phi into even/odd cb fields: lex = x + Lx(y + Ly(z + Lz t)), cb = lex >> 1
+    Lx, Ly, Lz, Lt = w.L
+    t, z, y, x = np.meshgrid(np.arange(Lt), np.arange(Lz), np.arange(Ly), np.arange(Lx), indexing="ij")
+    parity = ((x + y + z + t) % 2).ravel()
+    lex = np.arange(A.V)
+    fields = {}
+    for p in (0, 1):
+        sel = lex[parity == p]
+        cbf = np.zeros((w.nrhs, A.V // 2, w.Ls, 4, 3), np.complex128)
+        cbf[:, sel >> 1] = phi[:, sel]
+        fields[p] = h.upload(cbf, p)
+    del phi
+    b = h.field(M.F64, w.nrhs, 0)
+    h.prepare_rhs(b, fields[0], fields[1])
+    torch.cuda.synchronize()
+    return h, A, U, eps, b
+
+
+def time_dslash(h, A, w, prec, reps=50, warm=5):
+    """Median duration of one dslash_eo launch (HIP events on the launch stream)."""
+    import torch
+
+    stream = torch.cuda.Stream()
+    fin = h.field(prec, w.nrhs, 1)
+    fout = h.field(prec, w.nrhs, 0)
+    with torch.cuda.stream(stream):
+        src = h.upload(synth.cb_field(w.L, w.Ls, w.nrhs, 99), 1, M.F64)
+        h.convert(fin, src, stream=stream)
+        for _ in range(warm):
+            h.dslash_eo(fout, fin, 0, stream=stream)
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            h.dslash_eo(fout, fin, 0, stream=stream)
+            e1.record(stream)
+            times.append((e0, e1))
+        stream.synchronize()
+    ms = float(np.median([a.elapsed_time(b) for a, b in times]))
+    nsites5 = (A.V // 2) * w.Ls * w.nrhs
+    bytes_ = dslash_bytes_per_site(prec, w.Ls, w.nrhs) * nsites5
+    return {"ms": ms, "bytes": bytes_, "gbs": bytes_ / (ms * 1e-3) / 1e9}
+
+
+def cpu_baseline(w, U, outer_iters, n_inner, nblk, budget_s=20.0):
+    """Oracle (FP64 C++/OpenMP) per-application time on the full lattice, projected to a solve."""
+    import oracle as O
+
+    oa = O.Action(w.L, w.Ls, M5=w.M5, mf=w.mf, b=w.b, c=w.c)
+    x = synth.cb_field(w.L, w.Ls, 1, 5)[0]
+    t0 = time.time()
+    n = 0
+    while n < 1 or (time.time() - t0 < budget_s / 2 and n < 3):
+        O.mdagm(oa, U, x)
+        n += 1
+    t_A = (time.time() - t0) / n
+    nb = int(np.prod(nblk))
+    # the oracle's preconditioner applies its literal A_s (one full-lattice A per block)
+    a_per_outer = 1 + n_inner * nb
+    a_total = outer_iters * a_per_outer + 2
+    return {
+        "value": t_A * a_total,
+        "unit": "s",
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": f"{n} full-lattice applications of A = D_PC^+ D_PC ({t_A:.2f} s each), projected to the "
+                  f"{a_total} applications of the oracle's MSPCG at the GPU's {outer_iters} outer iterations",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mobius_16x16x16x32_ls16")
+    ap.add_argument("--inner-prec", default=None)
+    ap.add_argument("--n-inner", type=int, default=None)
+    ap.add_argument("--cg-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (the method's "
+              "sharding is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    w = WORKLOADS[args.workload]
+    inner_prec = PREC[args.inner_prec or w.inner_prec]
+    k = args.n_inner if args.n_inner is not None else w.n_inner
+    nblk = w.nblk
+    h, A, U, eps, b = build_problem(w, torch)
+    x = h.field(M.F64, w.nrhs, 0)
+
+    def mspcg_step():
+        x.data.zero_()
+        return h.mspcg_solve(x, b, nblk, k, inner_prec, tol=w.tol, max_iter=20000, reliable=w.reliable)
+
+    def cg_step():
+        x.data.zero_()
+        return h.cg_solve(x, b, tol=w.tol, max_iter=50000, reliable=w.reliable)
+
+    for i in range(args.warmup):
+        st = mspcg_step()
+        log(f"[bench] warmup mspcg {i}: {st['outer_iters']} outer, {st['seconds']:.3f}s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for i in range(args.steps):
+        stats.append(mspcg_step())
+        log(f"[bench] step {i}: {stats[-1]['outer_iters']} outer, {stats[-1]['seconds']:.3f}s")
+    torch.cuda.synchronize()
+    t_ms = (time.perf_counter() - t0) / args.steps
+
+    cg_stats, t_cg = None, None
+    if args.cg_steps > 0:
+        cg_step()  # warm
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(args.cg_steps):
+            cg_stats = cg_step()
+            log(f"[bench] plain CG {i}: {cg_stats['outer_iters']} iterations, {cg_stats['seconds']:.3f}s")
+        torch.cuda.synchronize()
+        t_cg = (time.perf_counter() - t1) / args.cg_steps
+
+    dsl = {p: time_dslash(h, A, w, PREC[p]) for p in ("f64", "f32", "f16")}
+    for p, d in dsl.items():
+        log(f"[bench] dslash_eo {p}: {d['ms'] * 1e3:.1f} us, {d['gbs']:.0f} GB/s")
+    main_k = dsl["f64"]
+    out = {
+        "metric": METRIC,
+        "value": t_ms,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_ms * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+" + {M.F32: "f32", M.F16: "f16", M.BF16: "bf16", M.F64: "f64"}[inner_prec],
+        "data": "synthetic",
+        "config": {
+            "workload": w.name, "lattice": list(w.L), "Ls": w.Ls, "nrhs": w.nrhs, "mobius_b_c": [w.b, w.c],
+            "M5": w.M5, "mf": w.mf, "blocks": list(nblk), "n_inner": k, "tol": w.tol, "reliable": w.reliable,
+            "gauge_eps": round(eps, 5),
+        },
+        "mspcg": {"seconds": t_ms, "outer_iters": stats[-1]["outer_iters"], "inner_iters": stats[-1]["inner_iters"],
+                  "true_rel_resid": stats[-1]["true_rel_resid"]},
+        "plain_cg": None if cg_stats is None else {
+            "seconds": t_cg, "iters": cg_stats["outer_iters"], "true_rel_resid": cg_stats["true_rel_resid"]},
+        "mspcg_speedup_vs_cg": None if t_cg is None else t_cg / t_ms,
+        "dslash_eo": {p: {"us": d["ms"] * 1e3, "GB/s": d["gbs"], "frac_hbm": d["gbs"] / HBM_PEAK_GBS}
+                      for p, d in dsl.items()},
+        "roofline": {"bound": "hbm", "achieved": main_k["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": main_k["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": "hop_kernel f64 (dslash_eo)"},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, U, stats[-1]["outer_iters"], k, nblk)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

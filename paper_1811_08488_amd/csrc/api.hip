@@ -1,0 +1,1058 @@
+// C-ABI entry points: handle, geometry tables, operators, the batched block
+// CG preconditioner and the two FP64 outer solvers (Algorithm 1 with and
+// without the multisplitting preconditioner).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace mspcg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Fail {
+  mspcg_status st;
+};
+
+void fail(mspcg_status st, const std::string &msg) {
+  g_last_error = msg;
+  throw Fail{st};
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) fail(MSPCG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Device buffer owned by the handle.
+struct DBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+  ~DBuf() {
+    if (p) (void)hipFree(p);
+  }
+  void ensure(size_t n) {
+    if (n <= bytes) return;
+    if (p) {
+      (void)hipFree(p);
+      p = nullptr;
+      bytes = 0;
+    }
+    if (n == 0) return;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(MSPCG_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");
+    }
+    bytes = n;
+  }
+  template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+template <typename T>
+void upload(DBuf &b, const std::vector<T> &v, hipStream_t st) {
+  b.ensure(v.size() * sizeof(T) + 16);
+  if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+size_t prec_bytes(int prec) { return prec == MSPCG_F64 ? 8 : prec == MSPCG_F32 ? 4 : 2; }
+bool prec_norm(int prec) { return prec == MSPCG_F16 || prec == MSPCG_BF16; }
+
+// A [nrhs][nsites][Ls][24] vector of one precision owned by the handle.
+struct OwnedVec {
+  DBuf data, norm;
+  Vec v;
+  void ensure(int prec, int nrhs, long long nsites, int Ls) {
+    const size_t n5 = (size_t)nrhs * nsites * Ls;
+    data.ensure(n5 * 24 * prec_bytes(prec));
+    if (prec_norm(prec)) norm.ensure(n5 * sizeof(float));
+    v.data = data.p;
+    v.norm = prec_norm(prec) ? norm.as<float>() : nullptr;
+    v.prec = prec;
+    v.stride = nsites;
+  }
+};
+
+// Halo-extended block domains of one blocking (Sec. 2.3: the block operator
+// keeps every path of the four hops that leaves the block and comes back).
+struct BlockGeom {
+  int nblk[4];
+  int nb = 0;
+  int be_tot = 0, o1_tot = 0, e2_tot = 0;
+  std::vector<int> be_off, o1_off, e2_off;   // padded offsets, size nb+1
+  std::vector<int> be_n, o1_n, e2_n;         // true counts
+  std::vector<int> be_lex, o1_lex, e2_lex;   // lex per padded entry (-1 padding)
+  DBuf d_be_cb, d_be_blk, d_be_nbr, d_be_e2, d_o1_cb, d_o1_nbr_be, d_o1_nbr_e2, d_e2_cb, d_e2_nbr, d_e2_be, d_be_off;
+  // work vectors (inner precision)
+  int vprec = -1, vnrhs = 0;
+  OwnedVec x, r, p, Ap, o1v, e2v;
+  DBuf partial, scal, rrbuf;
+};
+
+constexpr int kPad = 64;  // block lists are padded to multiples of this many sites
+
+}  // namespace
+
+struct mspcg_handle {
+  mspcg_dwf par;
+  int V = 0, Vh = 0, Lxyz = 0;
+  hipStream_t stream = nullptr;
+  double alpha5 = 0, beta5 = 0;  // M_5 = alpha5 - beta5 P_chi
+  // global tables per parity: site list (identity), neighbours (cb of the other parity)
+  DBuf d_iota, d_nbr[2], d_lex[2], d_nbrlex[2];
+  std::vector<int> lex_of_cb[2], nbr_cb[2];
+  DBuf links[4][2];
+  bool links_ok[4] = {false, false, false, false};
+  DBuf d_gauge;
+  // dense fifth-dimension matrices [2][Ls][Ls]
+  DBuf d_m5inv, d_m5inv_t, d_x1, d_x3;
+  // FP64 workspaces
+  OwnedVec tmp_o, tmp_e, tmp_o2, tmp_e2, sr, sp, sq, sz;
+  DBuf partial, scal;
+  std::map<std::vector<int>, std::unique_ptr<BlockGeom>> blocks;
+};
+
+namespace {
+
+template <typename F>
+mspcg_status guarded(F &&f) {
+  try {
+    g_last_error.clear();
+    f();
+    return MSPCG_OK;
+  } catch (const Fail &e) {
+    return e.st;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return MSPCG_EINVAL;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return MSPCG_EINVAL;
+  }
+}
+
+hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// sites per workgroup: the largest power of two with <= 256 threads (>= 1)
+int pick_nsite(int nrhs, int Ls) {
+  int n = 1;
+  while (n * 2 <= kPad && n * 2 * nrhs * Ls <= 256) n *= 2;
+  return n;
+}
+
+// ------------------------------------------------------------- fifth dimension
+// Per chirality the operators are Ls x Ls real matrices: on chirality +
+// P_chi acts as S-, on chirality - as S+ (S^Ls = -mf).
+typedef std::vector<double> Mat;  // row-major Ls x Ls
+
+Mat shift(int Ls, double mf, bool up) {
+  Mat S(Ls * Ls, 0.0);
+  for (int s = 0; s < Ls; ++s) {
+    if (up) {
+      if (s < Ls - 1) S[s * Ls + s + 1] = 1; else S[s * Ls + 0] = -mf;
+    } else {
+      if (s > 0) S[s * Ls + s - 1] = 1; else S[s * Ls + Ls - 1] = -mf;
+    }
+  }
+  return S;
+}
+Mat matmul(const Mat &A, const Mat &B, int n) {
+  Mat C(n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j) C[i * n + j] += A[i * n + k] * B[k * n + j];
+  return C;
+}
+Mat transpose(const Mat &A, int n) {
+  Mat T(n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) T[j * n + i] = A[i * n + j];
+  return T;
+}
+// (alpha - beta S)^{-1} = sum_k q^k S^k / (alpha (1 + mf q^Ls)),  q = beta / alpha
+Mat m5inv_chiral(int Ls, double alpha, double beta, double mf, bool up) {
+  Mat S = shift(Ls, mf, up), P(Ls * Ls, 0.0), acc(Ls * Ls, 0.0);
+  for (int i = 0; i < Ls; ++i) P[i * Ls + i] = 1;
+  const double q = beta / alpha;
+  double qk = 1;
+  for (int k = 0; k < Ls; ++k) {
+    for (int i = 0; i < Ls * Ls; ++i) acc[i] += qk * P[i];
+    P = matmul(P, S, Ls);
+    qk *= q;
+  }
+  const double den = alpha * (1 + mf * std::pow(q, Ls));
+  for (auto &x : acc) x /= den;
+  return acc;
+}
+Mat mphi_chiral(int Ls, double b, double c, double mf, bool up) {
+  Mat M = shift(Ls, mf, up);
+  for (auto &x : M) x *= c;
+  for (int i = 0; i < Ls; ++i) M[i * Ls + i] += b;
+  return M;
+}
+std::vector<double> pack2(const Mat &plus, const Mat &minus) {
+  std::vector<double> v(plus);
+  v.insert(v.end(), minus.begin(), minus.end());
+  return v;
+}
+
+// ------------------------------------------------------------- validation
+void check_field(mspcg_handle *h, const mspcg_field *f, const char *name) {
+  if (!f || !f->data) fail(MSPCG_EINVAL, std::string(name) + ": NULL field");
+  if (f->nrhs < 1) fail(MSPCG_EINVAL, std::string(name) + ": nrhs < 1");
+  if (f->nrhs > MSPCG_MAX_NRHS) fail(MSPCG_EUNSUPPORTED, std::string(name) + ": nrhs above MSPCG_MAX_NRHS");
+  if (f->parity != 0 && f->parity != 1) fail(MSPCG_EINVAL, std::string(name) + ": parity must be 0 or 1");
+  if (f->prec < MSPCG_F64 || f->prec > MSPCG_BF16) fail(MSPCG_EINVAL, std::string(name) + ": unknown precision");
+  if (prec_norm(f->prec) && !f->norm) fail(MSPCG_EINVAL, std::string(name) + ": F16/BF16 field without norm array");
+  if (f->nrhs * h->par.Ls > 256) fail(MSPCG_EUNSUPPORTED, std::string(name) + ": nrhs * Ls above 256");
+}
+
+Vec vec_of(mspcg_handle *h, const mspcg_field *f) {
+  Vec v;
+  v.data = f->data;
+  v.norm = f->norm;
+  v.prec = f->prec;
+  v.stride = h->Vh;
+  return v;
+}
+
+// ------------------------------------------------------------- gauge / links
+void ensure_links(mspcg_handle *h, int prec, hipStream_t st) {
+  if (h->links_ok[prec]) return;
+  for (int p = 0; p < 2; ++p) {
+    h->links[prec][p].ensure((size_t)h->Vh * 8 * 18 * prec_bytes(prec));
+    HIPCHK(pack_links(prec, h->links[prec][p].p, h->d_gauge.as<double>(), h->d_lex[p].as<int>(),
+                      h->d_nbrlex[p].as<int>(), p, h->Vh, h->par.L[3], h->Lxyz, (double)h->par.t_bc, st));
+  }
+  h->links_ok[prec] = true;
+}
+
+// ------------------------------------------------------------- hop launches
+HopArgs base_args(mspcg_handle *h, int nrhs) {
+  HopArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.Ls = h->par.Ls;
+  a.nrhs = nrhs;
+  a.nsite_wg = pick_nsite(nrhs, h->par.Ls);
+  a.mphi_b = h->par.b;
+  a.mphi_c = h->par.c;
+  a.mf = h->par.mf;
+  a.m5_alpha = h->alpha5;
+  a.m5_beta = h->beta5;
+  return a;
+}
+
+// Full-lattice hop: output parity p (site list = all cb), input parity 1-p.
+void global_hop(mspcg_handle *h, int prec, int nrhs, int p, const Vec &out, const Vec &in, int dag, int pre, int epi,
+                double scale, const double *mat, const Vec *other, double *partial, const Vec *dotw,
+                hipStream_t st) {
+  ensure_links(h, prec, st);
+  HopArgs a = base_args(h, nrhs);
+  a.nsites = h->Vh;
+  a.site_cb = h->d_iota.as<int>();
+  a.nbr = h->d_nbr[p].as<int>();
+  a.in = in.data;
+  a.in_norm = in.norm;
+  a.in_stride = h->Vh;
+  a.out = out.data;
+  a.out_norm = out.norm;
+  a.out_stride = h->Vh;
+  a.links = h->links[prec][p].p;
+  a.scale = scale;
+  a.mat = mat;
+  if (other) {
+    a.other = other->data;
+    a.other_norm = other->norm;
+    a.other_stride = h->Vh;
+  }
+  if (partial) {
+    a.partial = partial;
+    a.dotw = dotw->data;
+    a.dotw_norm = dotw->norm;
+    a.dotw_stride = h->Vh;
+  }
+  HIPCHK(launch_hop(prec, dag, pre, epi, partial ? 1 : 0, a, st));
+}
+
+int hop_grid(mspcg_handle *h, int nsites, int nrhs) {
+  const int n = pick_nsite(nrhs, h->par.Ls);
+  return (nsites + n - 1) / n;
+}
+
+// out_e = D_PC^+ D_PC in_e (all four hops fused with their fifth-dimension
+// neighbours); optional partial Re<in, out> per workgroup.
+void apply_mdagm(mspcg_handle *h, int prec, int nrhs, const Vec &out, const Vec &in, const Vec &to, const Vec &te,
+                 double *partial, hipStream_t st) {
+  // c_o = M_phi M_5^{-1} (-1/2 H_oe M_phi in)
+  global_hop(h, prec, nrhs, 1, to, in, 0, 1, EPI_DENSE, -0.5, h->d_x1.as<double>(), nullptr, nullptr, nullptr, st);
+  // y_e = M_5 in + 1/2 H_eo c_o  (= D_PC in)
+  global_hop(h, prec, nrhs, 0, te, to, 0, 0, EPI_M5_OTHER, 0.5, nullptr, &in, nullptr, nullptr, st);
+  // f_o = M_5^{-+} M_phi^+ (-1/2 H^+_oe y_e)
+  global_hop(h, prec, nrhs, 1, to, te, 1, 0, EPI_DENSE, -0.5, h->d_x3.as<double>(), nullptr, nullptr, nullptr, st);
+  // out = M_5^+ y + 1/2 M_phi^+ H^+_eo f  (= D_PC^+ y)
+  global_hop(h, prec, nrhs, 0, out, to, 1, 0, EPI_M5DAG_MPHIDAG, 0.5, nullptr, &te, partial, &in, st);
+}
+
+void ensure_fp64_temps(mspcg_handle *h, int nrhs) {
+  h->tmp_o.ensure(MSPCG_F64, nrhs, h->Vh, h->par.Ls);
+  h->tmp_e.ensure(MSPCG_F64, nrhs, h->Vh, h->par.Ls);
+}
+
+// ------------------------------------------------------------- block geometry
+BlockGeom *get_blocks(mspcg_handle *h, const int nblk[4], hipStream_t st) {
+  std::vector<int> key(nblk, nblk + 4);
+  auto it = h->blocks.find(key);
+  if (it != h->blocks.end()) return it->second.get();
+  const int *L = h->par.L;
+  for (int mu = 0; mu < 4; ++mu) {
+    if (nblk[mu] < 1 || nblk[mu] > L[mu]) fail(MSPCG_EINVAL, "nblk out of range");
+    if (nblk[mu] >= 2 && L[mu] / nblk[mu] + (L[mu] % nblk[mu] ? 1 : 0) + 4 > L[mu])
+      fail(MSPCG_EUNSUPPORTED, "block halo of depth 2 would wrap onto itself (need L >= block + 4)");
+  }
+  auto bg = std::make_unique<BlockGeom>();
+  std::memcpy(bg->nblk, nblk, sizeof(bg->nblk));
+  bg->nb = nblk[0] * nblk[1] * nblk[2] * nblk[3];
+  const int V = h->V;
+  std::vector<int> e2_of_lex(V, -1), o1_of_lex(V, -1);  // per-block scratch maps
+  std::vector<int> be_cb, be_blk, be_nbr, be_e2, o1_cb, o1_nbr_be, o1_nbr_e2, e2_cb, e2_nbr, e2_be;
+  bg->be_off.push_back(0);
+  bg->o1_off.push_back(0);
+  bg->e2_off.push_back(0);
+  auto lex_of = [&](const int c[4]) { return c[0] + L[0] * (c[1] + L[1] * (c[2] + L[2] * c[3])); };
+  for (int b = 0; b < bg->nb; ++b) {
+    int jb[4], start[4], size[4], lo[4], hi[4];
+    for (int mu = 0, t = b; mu < 4; ++mu) {
+      jb[mu] = t % nblk[mu];
+      t /= nblk[mu];
+      const int q = L[mu] / nblk[mu], rr = L[mu] % nblk[mu];
+      start[mu] = jb[mu] * q + std::min(jb[mu], rr);
+      size[mu] = q + (jb[mu] < rr ? 1 : 0);
+      lo[mu] = nblk[mu] >= 2 ? -2 : 0;
+      hi[mu] = nblk[mu] >= 2 ? size[mu] + 2 : size[mu];
+    }
+    // enumerate the extended box in local lex order (x fastest)
+    std::vector<int> loc_be, loc_o1, loc_e2;
+    std::vector<int> dist_e2;
+    for (int ut = lo[3]; ut < hi[3]; ++ut)
+      for (int uz = lo[2]; uz < hi[2]; ++uz)
+        for (int uy = lo[1]; uy < hi[1]; ++uy)
+          for (int ux = lo[0]; ux < hi[0]; ++ux) {
+            const int u[4] = {ux, uy, uz, ut};
+            int dist = 0, c[4];
+            for (int mu = 0; mu < 4; ++mu) {
+              dist += std::max(0, std::max(-u[mu], u[mu] - (size[mu] - 1)));
+              c[mu] = ((start[mu] + u[mu]) % L[mu] + L[mu]) % L[mu];
+            }
+            const int g = lex_of(c);
+            const int par = (c[0] + c[1] + c[2] + c[3]) & 1;
+            if (par == 0 && dist <= 2) {
+              loc_e2.push_back(g);
+              dist_e2.push_back(dist);
+            }
+            if (par == 1 && dist <= 1) loc_o1.push_back(g);
+            if (par == 0 && dist == 0) loc_be.push_back(g);
+          }
+    const int be0 = bg->be_off.back(), o10 = bg->o1_off.back(), e20 = bg->e2_off.back();
+    const int nbe = (int)loc_be.size(), no1 = (int)loc_o1.size(), ne2 = (int)loc_e2.size();
+    const int pbe = (nbe + kPad - 1) / kPad * kPad, po1 = (no1 + kPad - 1) / kPad * kPad,
+              pe2 = (ne2 + kPad - 1) / kPad * kPad;
+    for (int i = 0; i < no1; ++i) o1_of_lex[loc_o1[i]] = o10 + i;
+    for (int i = 0; i < ne2; ++i) e2_of_lex[loc_e2[i]] = e20 + i;
+    std::vector<int> be_of_e2(ne2, -1);
+    {
+      int k = 0;
+      for (int i = 0; i < ne2; ++i)
+        if (dist_e2[i] == 0) be_of_e2[i] = be0 + k++;
+    }
+    auto nb_lex = [&](int g, int d) {
+      int c[4];
+      int t = g;
+      for (int mu = 0; mu < 4; ++mu) { c[mu] = t % L[mu]; t /= L[mu]; }
+      const int mu = d >> 1;
+      c[mu] = (c[mu] + ((d & 1) ? -1 : 1) + L[mu]) % L[mu];
+      return lex_of(c);
+    };
+    // E2 (even) -> O1 neighbours, map to B_e
+    for (int i = 0; i < pe2; ++i) {
+      if (i < ne2) {
+        const int g = loc_e2[i];
+        e2_cb.push_back(g >> 1);
+        for (int d = 0; d < 8; ++d) e2_nbr.push_back(o1_of_lex[nb_lex(g, d)]);
+        e2_be.push_back(be_of_e2[i]);
+        bg->e2_lex.push_back(g);
+      } else {
+        e2_cb.push_back(-1);
+        for (int d = 0; d < 8; ++d) e2_nbr.push_back(-1);
+        e2_be.push_back(-1);
+        bg->e2_lex.push_back(-1);
+      }
+    }
+    // O1 (odd) -> E2 / B_e neighbours
+    for (int i = 0; i < po1; ++i) {
+      if (i < no1) {
+        const int g = loc_o1[i];
+        o1_cb.push_back(g >> 1);
+        for (int d = 0; d < 8; ++d) {
+          const int e = e2_of_lex[nb_lex(g, d)];
+          o1_nbr_e2.push_back(e);
+          o1_nbr_be.push_back(e >= 0 ? be_of_e2[e - e20] : -1);
+        }
+        bg->o1_lex.push_back(g);
+      } else {
+        o1_cb.push_back(-1);
+        for (int d = 0; d < 8; ++d) { o1_nbr_e2.push_back(-1); o1_nbr_be.push_back(-1); }
+        bg->o1_lex.push_back(-1);
+      }
+    }
+    // B_e in block-local lex order; neighbours from its E2 entry
+    {
+      int k = 0;
+      for (int i = 0; i < ne2; ++i) {
+        if (dist_e2[i] != 0) continue;
+        const int g = loc_e2[i];
+        if (g != loc_be[k]) fail(MSPCG_EINVAL, "internal: block ordering mismatch");
+        be_cb.push_back(g >> 1);
+        be_blk.push_back(b);
+        be_e2.push_back(e20 + i);
+        for (int d = 0; d < 8; ++d) be_nbr.push_back(e2_nbr[(size_t)(e20 + i) * 8 + d]);
+        bg->be_lex.push_back(g);
+        ++k;
+      }
+      for (int i = nbe; i < pbe; ++i) {
+        be_cb.push_back(-1);
+        be_blk.push_back(-1);
+        be_e2.push_back(-1);
+        for (int d = 0; d < 8; ++d) be_nbr.push_back(-1);
+        bg->be_lex.push_back(-1);
+      }
+    }
+    for (int i = 0; i < no1; ++i) o1_of_lex[loc_o1[i]] = -1;
+    for (int i = 0; i < ne2; ++i) e2_of_lex[loc_e2[i]] = -1;
+    bg->be_n.push_back(nbe);
+    bg->o1_n.push_back(no1);
+    bg->e2_n.push_back(ne2);
+    bg->be_off.push_back(be0 + pbe);
+    bg->o1_off.push_back(o10 + po1);
+    bg->e2_off.push_back(e20 + pe2);
+  }
+  bg->be_tot = bg->be_off.back();
+  bg->o1_tot = bg->o1_off.back();
+  bg->e2_tot = bg->e2_off.back();
+  // every index must stay inside its list
+  for (int x : be_nbr) if (x >= bg->o1_tot) fail(MSPCG_EINVAL, "internal: B_e table out of range");
+  for (int x : e2_nbr) if (x >= bg->o1_tot) fail(MSPCG_EINVAL, "internal: E2 table out of range");
+  for (int x : o1_nbr_e2) if (x >= bg->e2_tot) fail(MSPCG_EINVAL, "internal: O1 table out of range");
+  for (int x : o1_nbr_be) if (x >= bg->be_tot) fail(MSPCG_EINVAL, "internal: O1 table out of range");
+  upload(bg->d_be_cb, be_cb, st);
+  upload(bg->d_be_blk, be_blk, st);
+  upload(bg->d_be_nbr, be_nbr, st);
+  upload(bg->d_be_e2, be_e2, st);
+  upload(bg->d_o1_cb, o1_cb, st);
+  upload(bg->d_o1_nbr_be, o1_nbr_be, st);
+  upload(bg->d_o1_nbr_e2, o1_nbr_e2, st);
+  upload(bg->d_e2_cb, e2_cb, st);
+  upload(bg->d_e2_nbr, e2_nbr, st);
+  upload(bg->d_e2_be, e2_be, st);
+  upload(bg->d_be_off, bg->be_off, st);
+  HIPCHK(hipStreamSynchronize(st));
+  BlockGeom *raw = bg.get();
+  h->blocks[key] = std::move(bg);
+  return raw;
+}
+
+void ensure_block_vecs(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs) {
+  const int Ls = h->par.Ls;
+  bg->x.ensure(prec, nrhs, bg->be_tot, Ls);
+  bg->r.ensure(prec, nrhs, bg->be_tot, Ls);
+  bg->p.ensure(prec, nrhs, bg->be_tot, Ls);
+  bg->Ap.ensure(prec, nrhs, bg->be_tot, Ls);
+  bg->o1v.ensure(prec, nrhs, bg->o1_tot, Ls);
+  bg->e2v.ensure(prec, nrhs, bg->e2_tot, Ls);
+  const int nwg = bg->be_tot;  // upper bound on workgroups (nsite_wg >= 1)
+  bg->partial.ensure((size_t)nwg * nrhs * sizeof(double));
+  bg->scal.ensure((size_t)bg->nb * nrhs * kScal * sizeof(double));
+  bg->rrbuf.ensure((size_t)nrhs * sizeof(double) + 16);
+  bg->vprec = prec;
+  bg->vnrhs = nrhs;
+}
+
+HopArgs block_hop_args(mspcg_handle *h, int nrhs, int nsites, const int *site_cb, const int *nbr, const Vec &in,
+                       const Vec &out, int out_parity, int prec) {
+  HopArgs a = base_args(h, nrhs);
+  a.nsites = nsites;
+  a.site_cb = site_cb;
+  a.nbr = nbr;
+  a.in = in.data;
+  a.in_norm = in.norm;
+  a.in_stride = in.stride;
+  a.out = out.data;
+  a.out_norm = out.norm;
+  a.out_stride = out.stride;
+  a.links = h->links[prec][out_parity].p;
+  return a;
+}
+
+// out = A_s in for every block at once on the halo-extended domains
+// (B_e -> O1 -> E2 -> O1 -> B_e); optional partial Re<in, out> per workgroup.
+void block_hops(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, const Vec &in, const Vec &out, double *partial,
+                hipStream_t st) {
+  HopArgs a1 = block_hop_args(h, nrhs, bg->o1_tot, bg->d_o1_cb.as<int>(), bg->d_o1_nbr_be.as<int>(), in,
+                              bg->o1v.v, 1, prec);
+  a1.scale = -0.5;
+  a1.mat = h->d_x1.as<double>();
+  HIPCHK(launch_hop(prec, 0, 1, EPI_DENSE, 0, a1, st));
+  HopArgs a2 = block_hop_args(h, nrhs, bg->e2_tot, bg->d_e2_cb.as<int>(), bg->d_e2_nbr.as<int>(), bg->o1v.v,
+                              bg->e2v.v, 0, prec);
+  a2.scale = 0.5;
+  a2.other = in.data;
+  a2.other_norm = in.norm;
+  a2.other_stride = in.stride;
+  a2.other_idx = bg->d_e2_be.as<int>();
+  HIPCHK(launch_hop(prec, 0, 0, EPI_M5_OTHER, 0, a2, st));
+  HopArgs a3 = block_hop_args(h, nrhs, bg->o1_tot, bg->d_o1_cb.as<int>(), bg->d_o1_nbr_e2.as<int>(), bg->e2v.v,
+                              bg->o1v.v, 1, prec);
+  a3.scale = -0.5;
+  a3.mat = h->d_x3.as<double>();
+  HIPCHK(launch_hop(prec, 1, 0, EPI_DENSE, 0, a3, st));
+  HopArgs a4 = block_hop_args(h, nrhs, bg->be_tot, bg->d_be_cb.as<int>(), bg->d_be_nbr.as<int>(), bg->o1v.v, out,
+                              0, prec);
+  a4.scale = 0.5;
+  a4.other = bg->e2v.v.data;
+  a4.other_norm = bg->e2v.v.norm;
+  a4.other_stride = bg->e2v.v.stride;
+  a4.other_idx = bg->d_be_e2.as<int>();
+  if (partial) {
+    a4.partial = partial;
+    a4.dotw = in.data;
+    a4.dotw_norm = in.norm;
+    a4.dotw_stride = in.stride;
+  }
+  HIPCHK(launch_hop(prec, 1, 0, EPI_M5DAG_MPHIDAG, partial ? 1 : 0, a4, st));
+}
+
+BlockArgs block_args(mspcg_handle *h, BlockGeom *bg, int nrhs) {
+  BlockArgs ba;
+  ba.nsites = bg->be_tot;
+  ba.Ls = h->par.Ls;
+  ba.nrhs = nrhs;
+  ba.nsite_wg = pick_nsite(nrhs, h->par.Ls);
+  ba.be_cb = bg->d_be_cb.as<int>();
+  ba.be_blk = bg->d_be_blk.as<int>();
+  ba.nblocks = bg->nb;
+  ba.be_off = bg->d_be_off.as<int>();
+  return ba;
+}
+
+// The preconditioner: z = sum_s P_s CG_k(A_s, P_s r) for every (block, rhs).
+// r, z: FP64 even fields.  rr: device |r|^2 per rhs (RMS scaling); partial_zr
+// (optional): workgroup partials of Re<z, r> for the outer solver.
+void run_block_cg(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int k, const Vec &z, const Vec &r,
+                  const double *rr, double *partial_zr, int *nparts_zr, hipStream_t st) {
+  ensure_links(h, prec, st);
+  ensure_block_vecs(h, bg, prec, nrhs);
+  const int Ls = h->par.Ls;
+  BlockArgs ba = block_args(h, bg, nrhs);
+  const double n_total = (double)h->Vh * Ls * 24;
+  double *part = bg->partial.as<double>();
+  double *scal = bg->scal.as<double>();
+  HIPCHK(block_gather(prec, ba, bg->x.v, bg->r.v, bg->p.v, r, rr, n_total, part, st));
+  HIPCHK(block_scalars(2, ba, part, scal, st));
+  for (int it = 0; it < k; ++it) {
+    block_hops(h, bg, prec, nrhs, bg->p.v, bg->Ap.v, part, st);
+    HIPCHK(block_scalars(0, ba, part, scal, st));
+    HIPCHK(block_update_xr(prec, ba, bg->x.v, bg->r.v, bg->p.v, bg->Ap.v, scal, part, st));
+    if (it + 1 < k) {
+      HIPCHK(block_scalars(1, ba, part, scal, st));
+      HIPCHK(block_update_p(prec, ba, bg->p.v, bg->r.v, scal, st));
+    }
+  }
+  HIPCHK(block_scatter(prec, ba, z, bg->x.v, r, rr, n_total, partial_zr ? partial_zr : part, st));
+  if (nparts_zr) *nparts_zr = (ba.nsites + ba.nsite_wg - 1) / ba.nsite_wg;
+}
+
+// ------------------------------------------------------------- solvers
+struct SolverWork {
+  double *rho, *pap, *alpha, *beta, *rr, *bb, *tmp;
+  int *active;
+};
+
+mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const mspcg_solver *s,
+                   const mspcg_precond *pc, mspcg_stats *st_out) {
+  mspcg_status result = MSPCG_OK;
+  mspcg_status rc = guarded([&] {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!h || !s) fail(MSPCG_EINVAL, "NULL handle or solver parameters");
+    check_field(h, x, "x");
+    check_field(h, b, "b");
+    if (x->prec != MSPCG_F64 || b->prec != MSPCG_F64) fail(MSPCG_EINVAL, "solvers take F64 fields");
+    if (x->parity != 0 || b->parity != 0) fail(MSPCG_EINVAL, "solvers work on even sites");
+    if (x->nrhs != b->nrhs) fail(MSPCG_EINVAL, "x and b differ in nrhs");
+    if (!(s->tol > 0) || s->max_iter < 0 || s->reliable_interval < 0) fail(MSPCG_EINVAL, "bad solver parameters");
+    if (pc) {
+      if (pc->n_inner < 0) fail(MSPCG_EINVAL, "n_inner < 0");
+      if (pc->inner_prec < MSPCG_F64 || pc->inner_prec > MSPCG_BF16) fail(MSPCG_EINVAL, "bad inner precision");
+    }
+    hipStream_t st = h->stream;
+    const int nrhs = b->nrhs, Ls = h->par.Ls;
+    const long long n = (long long)h->Vh * Ls * 24;
+    BlockGeom *bg = pc ? get_blocks(h, pc->nblk, st) : nullptr;
+    ensure_fp64_temps(h, nrhs);
+    h->sr.ensure(MSPCG_F64, nrhs, h->Vh, Ls);
+    h->sp.ensure(MSPCG_F64, nrhs, h->Vh, Ls);
+    h->sq.ensure(MSPCG_F64, nrhs, h->Vh, Ls);
+    if (pc) h->sz.ensure(MSPCG_F64, nrhs, h->Vh, Ls);
+    const int hop_parts = hop_grid(h, h->Vh, nrhs);
+    const size_t nparts_max = std::max<size_t>((size_t)std::max(hop_parts, kBlasGrid), bg ? (size_t)bg->be_tot : 0);
+    h->partial.ensure(nparts_max * nrhs * sizeof(double));
+    h->scal.ensure((size_t)nrhs * 8 * sizeof(double) + 64);
+    double *part = h->partial.as<double>();
+    SolverWork w;
+    w.rho = h->scal.as<double>();
+    w.pap = w.rho + nrhs;
+    w.alpha = w.pap + nrhs;
+    w.beta = w.alpha + nrhs;
+    w.rr = w.beta + nrhs;
+    w.bb = w.rr + nrhs;
+    w.tmp = w.bb + nrhs;
+    w.active = reinterpret_cast<int *>(w.tmp + nrhs);
+    Vec X = vec_of(h, x), B = vec_of(h, b), R = h->sr.v, P = h->sp.v, Q = h->sq.v;
+    Vec Z = pc ? h->sz.v : R;
+    double *xd = (double *)X.data, *bd = (double *)B.data, *rd = (double *)R.data, *pd = (double *)P.data,
+           *qd = (double *)Q.data, *zd = (double *)Z.data;
+    std::vector<double> hb(nrhs), hr(nrhs);
+    std::vector<int> active(nrhs, 1);
+    auto norm2 = [&](const double *v, double *out) {
+      HIPCHK(blas_dot_partial(v, v, n, nrhs, part, st));
+      HIPCHK(blas_reduce(part, kBlasGrid, nrhs, out, st));
+    };
+    auto to_host = [&](const double *d, std::vector<double> &hv) {
+      HIPCHK(hipMemcpyAsync(hv.data(), d, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      for (double v : hv)
+        if (!std::isfinite(v)) fail(MSPCG_ENONFINITE, "non-finite value in a solver reduction");
+    };
+    auto push_active = [&] {
+      HIPCHK(hipMemcpyAsync(w.active, active.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+    };
+    auto true_residual = [&] {  // r = b - A x, rr
+      apply_mdagm(h, MSPCG_F64, nrhs, Q, X, h->tmp_o.v, h->tmp_e.v, nullptr, st);
+      HIPCHK(blas_axpby(rd, 1.0, bd, -1.0, qd, n, nrhs, st));
+      norm2(rd, w.rr);
+      to_host(w.rr, hr);
+    };
+    auto precond = [&] {  // z = M^{-1} r and rho_new = <z, r> into w.tmp
+      if (pc) {
+        int nparts = 0;
+        run_block_cg(h, bg, pc->inner_prec, nrhs, pc->n_inner, Z, R, w.rr, part, &nparts, st);
+        HIPCHK(blas_reduce(part, nparts, nrhs, w.tmp, st));
+      } else {
+        HIPCHK(hipMemcpyAsync(w.tmp, w.rr, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
+      }
+    };
+    const double tol2 = s->tol * s->tol;
+    norm2(bd, w.bb);
+    to_host(w.bb, hb);
+    for (int i = 0; i < nrhs; ++i)
+      if (hb[i] == 0.0) active[i] = 0;
+    // b = 0: x = 0 is the solution
+    for (int i = 0; i < nrhs; ++i)
+      if (hb[i] == 0.0) HIPCHK(hipMemsetAsync(xd + (size_t)i * n, 0, n * sizeof(double), st));
+    true_residual();
+    for (int i = 0; i < nrhs; ++i)
+      if (active[i] && hr[i] <= tol2 * hb[i]) active[i] = 0;
+    push_active();
+    int it = 0;
+    long long inner = 0;
+    bool any = false;
+    for (int a : active) any |= (a != 0);
+    if (any) {
+      precond();
+      if (pc) inner += pc->n_inner;
+      HIPCHK(blas_axpby(pd, 1.0, zd, 0.0, zd, n, nrhs, st));  // p = z
+      HIPCHK(hipMemcpyAsync(w.rho, w.tmp, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
+      while (it < s->max_iter) {
+        apply_mdagm(h, MSPCG_F64, nrhs, Q, P, h->tmp_o.v, h->tmp_e.v, part, st);
+        HIPCHK(blas_reduce(part, hop_parts, nrhs, w.pap, st));
+        HIPCHK(solver_scalars(0, nrhs, w.active, w.rho, w.pap, w.alpha, st));
+        HIPCHK(blas_update_xr(xd, rd, pd, qd, w.alpha, n, nrhs, part, st));
+        HIPCHK(blas_reduce(part, kBlasGrid, nrhs, w.rr, st));
+        ++it;
+        to_host(w.rr, hr);
+        bool check = false;
+        for (int i = 0; i < nrhs; ++i) check |= active[i] && hr[i] <= tol2 * hb[i];
+        const bool reliable = s->reliable_interval > 0 && it % s->reliable_interval == 0;
+        if (check || reliable) {
+          true_residual();
+          bool changed = false;
+          for (int i = 0; i < nrhs; ++i)
+            if (active[i] && hr[i] <= tol2 * hb[i]) { active[i] = 0; changed = true; }
+          if (changed) push_active();
+        }
+        any = false;
+        for (int a : active) any |= (a != 0);
+        if (!any) break;
+        precond();
+        if (pc) inner += pc->n_inner;
+        HIPCHK(solver_scalars(1, nrhs, w.active, w.rho, w.tmp, w.beta, st));
+        HIPCHK(blas_xpay(pd, zd, w.beta, n, nrhs, st));
+      }
+    }
+    // final true residual
+    true_residual();
+    bool conv = true;
+    for (int i = 0; i < nrhs; ++i) {
+      const double rel = hb[i] > 0 ? std::sqrt(hr[i] / hb[i]) : 0.0;
+      if (hb[i] > 0 && !(rel <= s->tol)) conv = false;
+      if (st_out && st_out->true_rel_resid) st_out->true_rel_resid[i] = rel;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    if (st_out) {
+      st_out->outer_iters = it;
+      st_out->inner_iters = inner;
+      st_out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      st_out->t_precond = 0;
+    }
+    result = conv ? MSPCG_OK : MSPCG_NOT_CONVERGED;
+  });
+  return rc != MSPCG_OK ? rc : result;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char *mspcg_last_error(void) { return g_last_error.c_str(); }
+
+mspcg_status mspcg_create(mspcg_handle **hp, const mspcg_dwf *p, const double *gauge, void *stream) {
+  if (!hp) {
+    g_last_error = "NULL handle pointer";
+    return MSPCG_EINVAL;
+  }
+  *hp = nullptr;
+  std::unique_ptr<mspcg_handle> h(new mspcg_handle);
+  mspcg_status rc = guarded([&] {
+    if (!p || !gauge) fail(MSPCG_EINVAL, "NULL parameters or gauge field");
+    for (int mu = 0; mu < 4; ++mu)
+      if (p->L[mu] < 2 || (p->L[mu] & 1)) fail(MSPCG_EINVAL, "every lattice extent must be even and >= 2");
+    if (p->Ls < 2) fail(MSPCG_EINVAL, "Ls < 2");
+    if (p->Ls > MSPCG_MAX_LS) fail(MSPCG_EUNSUPPORTED, "Ls above MSPCG_MAX_LS");
+    if (p->t_bc != 1 && p->t_bc != -1) fail(MSPCG_EINVAL, "t_bc must be +1 or -1");
+    if (!std::isfinite(p->M5) || !std::isfinite(p->mf) || !std::isfinite(p->b) || !std::isfinite(p->c))
+      fail(MSPCG_EINVAL, "non-finite action parameter");
+    long long V = 1;
+    for (int mu = 0; mu < 4; ++mu) V *= p->L[mu];
+    if (V > (1LL << 30)) fail(MSPCG_EUNSUPPORTED, "lattice volume too large for 32-bit site indices");
+    h->par = *p;
+    h->V = (int)V;
+    h->Vh = (int)(V / 2);
+    h->Lxyz = p->L[0] * p->L[1] * p->L[2];
+    h->stream = S(stream);
+    h->alpha5 = p->b * (4.0 - p->M5) + 1.0;
+    h->beta5 = 1.0 - p->c * (4.0 - p->M5);
+    const int Ls = p->Ls;
+    const double q = h->beta5 / h->alpha5;
+    if (std::abs(1 + p->mf * std::pow(q, Ls)) < 1e-300 || h->alpha5 == 0.0) fail(MSPCG_EINVAL, "M_5 is singular");
+    hipStream_t st = h->stream;
+    // index maps
+    const int *L = p->L;
+    const int Lxh = L[0] / 2;
+    std::vector<int> iota(h->Vh);
+    for (int i = 0; i < h->Vh; ++i) iota[i] = i;
+    upload(h->d_iota, iota, st);
+    for (int par = 0; par < 2; ++par) {
+      auto &lex = h->lex_of_cb[par];
+      auto &nbr = h->nbr_cb[par];
+      std::vector<int> nbrlex((size_t)h->Vh * 8);
+      lex.resize(h->Vh);
+      nbr.resize((size_t)h->Vh * 8);
+      for (int cb = 0; cb < h->Vh; ++cb) {
+        int c[4];
+        int rest = cb / Lxh;
+        c[1] = rest % L[1];
+        c[2] = (rest / L[1]) % L[2];
+        c[3] = rest / (L[1] * L[2]);
+        c[0] = 2 * (cb % Lxh) + ((par + c[1] + c[2] + c[3]) & 1);
+        lex[cb] = c[0] + L[0] * (c[1] + L[1] * (c[2] + L[2] * c[3]));
+        for (int d = 0; d < 8; ++d) {
+          int y[4] = {c[0], c[1], c[2], c[3]};
+          const int mu = d >> 1;
+          y[mu] = (y[mu] + ((d & 1) ? -1 : 1) + L[mu]) % L[mu];
+          const int yl = y[0] + L[0] * (y[1] + L[1] * (y[2] + L[2] * y[3]));
+          nbrlex[(size_t)cb * 8 + d] = yl;
+          nbr[(size_t)cb * 8 + d] = yl >> 1;
+        }
+      }
+      upload(h->d_lex[par], lex, st);
+      upload(h->d_nbr[par], nbr, st);
+      upload(h->d_nbrlex[par], nbrlex, st);
+    }
+    // gauge copy (physical links) for repacking in any precision
+    h->d_gauge.ensure((size_t)V * 4 * 18 * sizeof(double));
+    HIPCHK(hipMemcpyAsync(h->d_gauge.p, gauge, (size_t)V * 4 * 18 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    ensure_links(h.get(), MSPCG_F64, st);
+    // fifth-dimension matrices per chirality (+: S-, -: S+)
+    Mat ip = m5inv_chiral(Ls, h->alpha5, h->beta5, p->mf, false);
+    Mat im = m5inv_chiral(Ls, h->alpha5, h->beta5, p->mf, true);
+    Mat pp = mphi_chiral(Ls, p->b, p->c, p->mf, false);
+    Mat pm = mphi_chiral(Ls, p->b, p->c, p->mf, true);
+    Mat x1p = matmul(pp, ip, Ls), x1m = matmul(pm, im, Ls);
+    upload(h->d_m5inv, pack2(ip, im), st);
+    upload(h->d_m5inv_t, pack2(transpose(ip, Ls), transpose(im, Ls)), st);
+    upload(h->d_x1, pack2(x1p, x1m), st);
+    upload(h->d_x3, pack2(transpose(x1p, Ls), transpose(x1m, Ls)), st);
+    HIPCHK(hipStreamSynchronize(st));
+  });
+  if (rc == MSPCG_OK) *hp = h.release();
+  return rc;
+}
+
+mspcg_status mspcg_destroy(mspcg_handle *h) {
+  if (!h) return MSPCG_OK;
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+  return MSPCG_OK;
+}
+
+mspcg_status dslash_eo(mspcg_handle *h, mspcg_field *out, const mspcg_field *in, int dagger, void *stream) {
+  return guarded([&] {
+    if (!h) fail(MSPCG_EINVAL, "NULL handle");
+    check_field(h, out, "out");
+    check_field(h, in, "in");
+    if (out->parity == in->parity) fail(MSPCG_EINVAL, "dslash_eo: out and in must have opposite parity");
+    if (out->prec != in->prec || out->nrhs != in->nrhs) fail(MSPCG_EINVAL, "dslash_eo: precision/nrhs mismatch");
+    if (out->data == in->data) fail(MSPCG_EINVAL, "dslash_eo: out must not alias in");
+    const Vec o = vec_of(h, out), i = vec_of(h, in);
+    if (!dagger)
+      global_hop(h, in->prec, in->nrhs, out->parity, o, i, 0, 1, EPI_SCALE, -0.5, nullptr, nullptr, nullptr, nullptr,
+                 S(stream));
+    else
+      global_hop(h, in->prec, in->nrhs, out->parity, o, i, 1, 0, EPI_MPHIDAG, -0.5, nullptr, nullptr, nullptr, nullptr,
+                 S(stream));
+  });
+}
+
+mspcg_status m5inv(mspcg_handle *h, mspcg_field *out, const mspcg_field *in, int dagger, void *stream) {
+  return guarded([&] {
+    if (!h) fail(MSPCG_EINVAL, "NULL handle");
+    check_field(h, out, "out");
+    check_field(h, in, "in");
+    if (out->parity != in->parity) fail(MSPCG_EINVAL, "m5inv: out and in must have the same parity");
+    if (out->prec != in->prec || out->nrhs != in->nrhs) fail(MSPCG_EINVAL, "m5inv: precision/nrhs mismatch");
+    Op5Args a;
+    std::memset(&a, 0, sizeof(a));
+    a.nsites = h->Vh;
+    a.Ls = h->par.Ls;
+    a.nrhs = in->nrhs;
+    a.nsite_wg = pick_nsite(in->nrhs, h->par.Ls);
+    a.in = in->data;
+    a.in_norm = in->norm;
+    a.out = out->data;
+    a.out_norm = out->norm;
+    a.stride = h->Vh;
+    a.dense = 1;
+    a.mat = dagger ? h->d_m5inv_t.as<double>() : h->d_m5inv.as<double>();
+    HIPCHK(launch_op5(in->prec, a, S(stream)));
+  });
+}
+
+mspcg_status mdagm(mspcg_handle *h, mspcg_field *out, const mspcg_field *in, void *stream) {
+  return guarded([&] {
+    if (!h) fail(MSPCG_EINVAL, "NULL handle");
+    check_field(h, out, "out");
+    check_field(h, in, "in");
+    if (out->parity != 0 || in->parity != 0) fail(MSPCG_EINVAL, "mdagm acts on even fields");
+    if (out->prec != in->prec || out->nrhs != in->nrhs) fail(MSPCG_EINVAL, "mdagm: precision/nrhs mismatch");
+    if (out->data == in->data) fail(MSPCG_EINVAL, "mdagm: out must not alias in");
+    const int prec = in->prec, nrhs = in->nrhs;
+    h->tmp_o2.ensure(prec, nrhs, h->Vh, h->par.Ls);
+    h->tmp_e2.ensure(prec, nrhs, h->Vh, h->par.Ls);
+    apply_mdagm(h, prec, nrhs, vec_of(h, out), vec_of(h, in), h->tmp_o2.v, h->tmp_e2.v, nullptr, S(stream));
+  });
+}
+
+mspcg_status local_block_cg(mspcg_handle *h, mspcg_field *z, const mspcg_field *r, const mspcg_precond *pc,
+                            void *stream) {
+  return guarded([&] {
+    if (!h || !pc) fail(MSPCG_EINVAL, "NULL handle or preconditioner");
+    check_field(h, z, "z");
+    check_field(h, r, "r");
+    if (z->prec != MSPCG_F64 || r->prec != MSPCG_F64) fail(MSPCG_EUNSUPPORTED, "local_block_cg takes F64 r and z");
+    if (z->parity != 0 || r->parity != 0) fail(MSPCG_EINVAL, "local_block_cg works on even sites");
+    if (z->nrhs != r->nrhs) fail(MSPCG_EINVAL, "nrhs mismatch");
+    if (pc->n_inner < 0) fail(MSPCG_EINVAL, "n_inner < 0");
+    if (pc->inner_prec < MSPCG_F64 || pc->inner_prec > MSPCG_BF16) fail(MSPCG_EINVAL, "bad inner precision");
+    hipStream_t st = S(stream);
+    BlockGeom *bg = get_blocks(h, pc->nblk, st);
+    const int nrhs = r->nrhs;
+    const long long n = (long long)h->Vh * h->par.Ls * 24;
+    ensure_block_vecs(h, bg, pc->inner_prec, nrhs);
+    h->partial.ensure((size_t)std::max(kBlasGrid, bg->be_tot) * nrhs * sizeof(double));
+    double *rr = bg->rrbuf.as<double>();
+    HIPCHK(blas_dot_partial((const double *)r->data, (const double *)r->data, n, nrhs, h->partial.as<double>(), st));
+    HIPCHK(blas_reduce(h->partial.as<double>(), kBlasGrid, nrhs, rr, st));
+    run_block_cg(h, bg, pc->inner_prec, nrhs, pc->n_inner, vec_of(h, z), vec_of(h, r), rr, nullptr, nullptr, st);
+  });
+}
+
+mspcg_status cg_solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const mspcg_solver *s,
+                      mspcg_stats *st) {
+  return solve(h, x, b, s, nullptr, st);
+}
+
+mspcg_status mspcg_solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const mspcg_solver *s,
+                         const mspcg_precond *pc, mspcg_stats *st) {
+  if (!pc) {
+    g_last_error = "NULL preconditioner";
+    return MSPCG_EINVAL;
+  }
+  return solve(h, x, b, s, pc, st);
+}
+
+mspcg_status dwf_prepare_rhs(mspcg_handle *h, mspcg_field *b, const mspcg_field *phi_e, const mspcg_field *phi_o,
+                             void *stream) {
+  return guarded([&] {
+    if (!h) fail(MSPCG_EINVAL, "NULL handle");
+    check_field(h, b, "b");
+    check_field(h, phi_e, "phi_e");
+    check_field(h, phi_o, "phi_o");
+    if (b->prec != MSPCG_F64 || phi_e->prec != MSPCG_F64 || phi_o->prec != MSPCG_F64)
+      fail(MSPCG_EINVAL, "dwf_prepare_rhs takes F64 fields");
+    if (b->parity != 0 || phi_e->parity != 0 || phi_o->parity != 1) fail(MSPCG_EINVAL, "parity mismatch");
+    const int nrhs = b->nrhs;
+    if (phi_e->nrhs != nrhs || phi_o->nrhs != nrhs) fail(MSPCG_EINVAL, "nrhs mismatch");
+    hipStream_t st = S(stream);
+    ensure_fp64_temps(h, nrhs);
+    const long long n = (long long)h->Vh * h->par.Ls * 24;
+    const Vec to = h->tmp_o.v, te = h->tmp_e.v;
+    // t_o = M_5^{-1} phi_o
+    Op5Args a;
+    std::memset(&a, 0, sizeof(a));
+    a.nsites = h->Vh;
+    a.Ls = h->par.Ls;
+    a.nrhs = nrhs;
+    a.nsite_wg = pick_nsite(nrhs, h->par.Ls);
+    a.in = phi_o->data;
+    a.out = to.data;
+    a.stride = h->Vh;
+    a.dense = 1;
+    a.mat = h->d_m5inv.as<double>();
+    HIPCHK(launch_op5(MSPCG_F64, a, st));
+    // te = M^4_eo t_o ; phihat = phi_e - te (into te)
+    global_hop(h, MSPCG_F64, nrhs, 0, te, to, 0, 1, EPI_SCALE, -0.5, nullptr, nullptr, nullptr, nullptr, st);
+    HIPCHK(blas_axpby((double *)te.data, 1.0, (const double *)phi_e->data, -1.0, (const double *)te.data, n, nrhs, st));
+    // b = D_PC^+ phihat
+    global_hop(h, MSPCG_F64, nrhs, 1, to, te, 1, 0, EPI_DENSE, -0.5, h->d_x3.as<double>(), nullptr, nullptr, nullptr,
+               st);
+    global_hop(h, MSPCG_F64, nrhs, 0, vec_of(h, b), to, 1, 0, EPI_M5DAG_MPHIDAG, 0.5, nullptr, &te, nullptr, nullptr,
+               st);
+    HIPCHK(hipStreamSynchronize(st));
+  });
+}
+
+mspcg_status dwf_reconstruct(mspcg_handle *h, mspcg_field *psi_o, const mspcg_field *psi_e, const mspcg_field *phi_o,
+                             void *stream) {
+  return guarded([&] {
+    if (!h) fail(MSPCG_EINVAL, "NULL handle");
+    check_field(h, psi_o, "psi_o");
+    check_field(h, psi_e, "psi_e");
+    check_field(h, phi_o, "phi_o");
+    if (psi_o->prec != MSPCG_F64 || psi_e->prec != MSPCG_F64 || phi_o->prec != MSPCG_F64)
+      fail(MSPCG_EINVAL, "dwf_reconstruct takes F64 fields");
+    if (psi_o->parity != 1 || psi_e->parity != 0 || phi_o->parity != 1) fail(MSPCG_EINVAL, "parity mismatch");
+    const int nrhs = psi_o->nrhs;
+    if (psi_e->nrhs != nrhs || phi_o->nrhs != nrhs) fail(MSPCG_EINVAL, "nrhs mismatch");
+    hipStream_t st = S(stream);
+    ensure_fp64_temps(h, nrhs);
+    const long long n = (long long)h->Vh * h->par.Ls * 24;
+    const Vec to = h->tmp_o.v;
+    // t = phi_o - M^4_oe psi_e ; psi_o = M_5^{-1} t
+    global_hop(h, MSPCG_F64, nrhs, 1, to, vec_of(h, psi_e), 0, 1, EPI_SCALE, -0.5, nullptr, nullptr, nullptr, nullptr,
+               st);
+    HIPCHK(blas_axpby((double *)to.data, 1.0, (const double *)phi_o->data, -1.0, (const double *)to.data, n, nrhs, st));
+    Op5Args a;
+    std::memset(&a, 0, sizeof(a));
+    a.nsites = h->Vh;
+    a.Ls = h->par.Ls;
+    a.nrhs = nrhs;
+    a.nsite_wg = pick_nsite(nrhs, h->par.Ls);
+    a.in = to.data;
+    a.out = psi_o->data;
+    a.stride = h->Vh;
+    a.dense = 1;
+    a.mat = h->d_m5inv.as<double>();
+    HIPCHK(launch_op5(MSPCG_F64, a, st));
+    HIPCHK(hipStreamSynchronize(st));
+  });
+}
+
+mspcg_status mspcg_debug_site_maps(mspcg_handle *h, int parity, int32_t *lex_of_cb, int32_t *nbr) {
+  return guarded([&] {
+    if (!h || (parity & ~1)) fail(MSPCG_EINVAL, "bad handle or parity");
+    if (lex_of_cb) std::memcpy(lex_of_cb, h->lex_of_cb[parity].data(), (size_t)h->Vh * sizeof(int32_t));
+    if (nbr) std::memcpy(nbr, h->nbr_cb[parity].data(), (size_t)h->Vh * 8 * sizeof(int32_t));
+  });
+}
+
+mspcg_status mspcg_debug_block_sites(mspcg_handle *h, const int nblk[4], int block, int32_t counts[3], int32_t *be_lex,
+                                     int32_t *o1_lex, int32_t *e2_lex) {
+  return guarded([&] {
+    if (!h || !nblk || !counts) fail(MSPCG_EINVAL, "NULL argument");
+    BlockGeom *bg = get_blocks(h, nblk, h->stream);
+    if (block < 0 || block >= bg->nb) fail(MSPCG_EINVAL, "block out of range");
+    counts[0] = bg->be_n[block];
+    counts[1] = bg->o1_n[block];
+    counts[2] = bg->e2_n[block];
+    if (be_lex) std::memcpy(be_lex, bg->be_lex.data() + bg->be_off[block], counts[0] * sizeof(int32_t));
+    if (o1_lex) std::memcpy(o1_lex, bg->o1_lex.data() + bg->o1_off[block], counts[1] * sizeof(int32_t));
+    if (e2_lex) std::memcpy(e2_lex, bg->e2_lex.data() + bg->e2_off[block], counts[2] * sizeof(int32_t));
+  });
+}
+
+mspcg_status mspcg_block_apply(mspcg_handle *h, mspcg_field *out, const mspcg_field *in, const int nblk[4], int prec,
+                               void *stream) {
+  return guarded([&] {
+    if (!h || !nblk) fail(MSPCG_EINVAL, "NULL argument");
+    check_field(h, out, "out");
+    check_field(h, in, "in");
+    if (out->prec != MSPCG_F64 || in->prec != MSPCG_F64) fail(MSPCG_EINVAL, "mspcg_block_apply takes F64 fields");
+    if (out->parity != 0 || in->parity != 0) fail(MSPCG_EINVAL, "mspcg_block_apply works on even sites");
+    if (out->nrhs != in->nrhs) fail(MSPCG_EINVAL, "nrhs mismatch");
+    if (prec < MSPCG_F64 || prec > MSPCG_BF16) fail(MSPCG_EINVAL, "bad precision");
+    if (out->data == in->data) fail(MSPCG_EINVAL, "out must not alias in");
+    hipStream_t st = S(stream);
+    BlockGeom *bg = get_blocks(h, nblk, st);
+    const int nrhs = in->nrhs;
+    ensure_links(h, prec, st);
+    ensure_block_vecs(h, bg, prec, nrhs);
+    BlockArgs ba = block_args(h, bg, nrhs);
+    const double n_total = (double)h->Vh * h->par.Ls * 24;
+    double *part = bg->partial.as<double>();
+    HIPCHK(block_gather(prec, ba, bg->x.v, bg->r.v, bg->p.v, vec_of(h, in), nullptr, n_total, part, st));
+    block_hops(h, bg, prec, nrhs, bg->p.v, bg->Ap.v, nullptr, st);
+    HIPCHK(block_scatter(prec, ba, vec_of(h, out), bg->Ap.v, Vec(), nullptr, n_total, part, st));
+  });
+}
+
+mspcg_status mspcg_convert(mspcg_handle *h, mspcg_field *out, const mspcg_field *in, void *stream) {
+  return guarded([&] {
+    if (!h) fail(MSPCG_EINVAL, "NULL handle");
+    check_field(h, out, "out");
+    check_field(h, in, "in");
+    if (out->nrhs != in->nrhs || out->parity != in->parity) fail(MSPCG_EINVAL, "convert: nrhs/parity mismatch");
+    HIPCHK(launch_convert(vec_of(h, out), vec_of(h, in), in->nrhs, (long long)h->Vh * h->par.Ls, S(stream)));
+  });
+}
+
+}  // extern "C"

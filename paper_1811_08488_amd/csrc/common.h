@@ -1,0 +1,288 @@
+// Device-side building blocks shared by the HIP kernels: storage traits for
+// the four field formats, 24-real site loads/stores, link loads and the
+// chiral-basis spin projection of the Wilson hop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mspcg {
+
+// ---------------------------------------------------------------- storage types
+struct bf16 {
+  uint16_t bits;
+};
+
+template <typename S> struct Traits;
+template <> struct Traits<double> {
+  using R = double;
+  static constexpr bool kNorm = false;
+};
+template <> struct Traits<float> {
+  using R = float;
+  static constexpr bool kNorm = false;
+};
+template <> struct Traits<_Float16> {
+  using R = float;
+  static constexpr bool kNorm = true;
+};
+template <> struct Traits<bf16> {
+  using R = float;
+  static constexpr bool kNorm = true;
+};
+
+// bfloat16 <-> float: widening is exact; narrowing rounds to nearest even.
+__device__ __host__ inline float bf16_to_float(uint16_t b) {
+  union { uint32_t u; float f; } c;
+  c.u = (uint32_t)b << 16;
+  return c.f;
+}
+__device__ __host__ inline uint16_t float_to_bf16(float f) {
+  union { uint32_t u; float f; } c;
+  c.f = f;
+  uint32_t u = c.u;
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// ---------------------------------------------------------------- site load/store
+// A 5D site holds 24 reals [spin][colour][re,im]; `site` counts 5D sites.
+template <typename R>
+__device__ inline void load24(const double *base, const float *, size_t site, R v[24]) {
+  const double2 *p = reinterpret_cast<const double2 *>(base + site * 24);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    double2 t = p[k];
+    v[2 * k] = (R)t.x;
+    v[2 * k + 1] = (R)t.y;
+  }
+}
+template <typename R>
+__device__ inline void load24(const float *base, const float *, size_t site, R v[24]) {
+  const float4 *p = reinterpret_cast<const float4 *>(base + site * 24);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    float4 t = p[k];
+    v[4 * k] = (R)t.x;
+    v[4 * k + 1] = (R)t.y;
+    v[4 * k + 2] = (R)t.z;
+    v[4 * k + 3] = (R)t.w;
+  }
+}
+template <typename R>
+__device__ inline void load24(const _Float16 *base, const float *norm, size_t site, R v[24]) {
+  const uint4 *p = reinterpret_cast<const uint4 *>(base + site * 24);
+  const float n = norm[site];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    uint4 t = p[k];
+    uint32_t w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      union { uint32_t u; _Float16 h[2]; } c;
+      c.u = w[j];
+      v[8 * k + 2 * j] = (R)((float)c.h[0] * n);
+      v[8 * k + 2 * j + 1] = (R)((float)c.h[1] * n);
+    }
+  }
+}
+template <typename R>
+__device__ inline void load24(const bf16 *base, const float *norm, size_t site, R v[24]) {
+  const uint4 *p = reinterpret_cast<const uint4 *>(base + site * 24);
+  const float n = norm[site];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    uint4 t = p[k];
+    uint32_t w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      v[8 * k + 2 * j] = (R)(bf16_to_float((uint16_t)(w[j] & 0xffffu)) * n);
+      v[8 * k + 2 * j + 1] = (R)(bf16_to_float((uint16_t)(w[j] >> 16)) * n);
+    }
+  }
+}
+
+template <typename R>
+__device__ inline void store24(double *base, float *, size_t site, const R v[24]) {
+  double2 *p = reinterpret_cast<double2 *>(base + site * 24);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) p[k] = make_double2((double)v[2 * k], (double)v[2 * k + 1]);
+}
+template <typename R>
+__device__ inline void store24(float *base, float *, size_t site, const R v[24]) {
+  float4 *p = reinterpret_cast<float4 *>(base + site * 24);
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    p[k] = make_float4((float)v[4 * k], (float)v[4 * k + 1], (float)v[4 * k + 2], (float)v[4 * k + 3]);
+}
+template <typename R>
+__device__ inline float site_scale(const R v[24], float &inv) {
+  float m = 0.f;
+#pragma unroll
+  for (int k = 0; k < 24; ++k) m = fmaxf(m, fabsf((float)v[k]));
+  inv = m > 0.f ? 1.f / m : 0.f;
+  return m;
+}
+template <typename R>
+__device__ inline void store24(_Float16 *base, float *norm, size_t site, const R v[24]) {
+  float inv;
+  norm[site] = site_scale(v, inv);
+  uint4 *p = reinterpret_cast<uint4 *>(base + site * 24);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    uint32_t w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      union { uint32_t u; _Float16 h[2]; } c;
+      c.h[0] = (_Float16)((float)v[8 * k + 2 * j] * inv);
+      c.h[1] = (_Float16)((float)v[8 * k + 2 * j + 1] * inv);
+      w[j] = c.u;
+    }
+    p[k] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+template <typename R>
+__device__ inline void store24(bf16 *base, float *norm, size_t site, const R v[24]) {
+  float inv;
+  norm[site] = site_scale(v, inv);
+  uint4 *p = reinterpret_cast<uint4 *>(base + site * 24);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    uint32_t w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      w[j] = (uint32_t)float_to_bf16((float)v[8 * k + 2 * j] * inv) |
+             ((uint32_t)float_to_bf16((float)v[8 * k + 2 * j + 1] * inv) << 16);
+    p[k] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+// ---------------------------------------------------------------- links
+// One 3x3 complex matrix = 18 reals [row][col][re,im]; stored in the
+// spinor storage type without a scale (|U_ij| <= 1).
+template <typename R>
+__device__ inline void load18(const double *base, size_t m, R u[18]) {
+  const double2 *p = reinterpret_cast<const double2 *>(base + m * 18);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    double2 t = p[k];
+    u[2 * k] = (R)t.x;
+    u[2 * k + 1] = (R)t.y;
+  }
+}
+template <typename R>
+__device__ inline void load18(const float *base, size_t m, R u[18]) {
+  const float2 *p = reinterpret_cast<const float2 *>(base + m * 18);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    float2 t = p[k];
+    u[2 * k] = (R)t.x;
+    u[2 * k + 1] = (R)t.y;
+  }
+}
+template <typename R>
+__device__ inline void load18(const _Float16 *base, size_t m, R u[18]) {
+  const uint32_t *p = reinterpret_cast<const uint32_t *>(base + m * 18);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    union { uint32_t u; _Float16 h[2]; } c;
+    c.u = p[k];
+    u[2 * k] = (R)(float)c.h[0];
+    u[2 * k + 1] = (R)(float)c.h[1];
+  }
+}
+template <typename R>
+__device__ inline void load18(const bf16 *base, size_t m, R u[18]) {
+  const uint32_t *p = reinterpret_cast<const uint32_t *>(base + m * 18);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    uint32_t w = p[k];
+    u[2 * k] = (R)bf16_to_float((uint16_t)(w & 0xffffu));
+    u[2 * k + 1] = (R)bf16_to_float((uint16_t)(w >> 16));
+  }
+}
+
+// ---------------------------------------------------------------- spin projection
+// Chiral basis: g_mu = [[0, B_mu], [B_mu^+, 0]] with B_k = -i sigma_k (k = x,y,z)
+// and B_t = 1.  For SGN = +1 the projector is (1 - g_mu), for SGN = -1 it is
+// (1 + g_mu).  (1 - SGN g_mu) psi has upper half h = u - SGN B l and lower half
+// -SGN B^+ h, so only h (2 spins x 3 colours) is multiplied by the link.
+// Indexing: v[(spin*3 + colour)*2 + ri], h[(k*3 + colour)*2 + ri], k = 0,1.
+template <int MU, int SGN, typename R>
+__device__ inline void project(const R v[24], R h[12]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const R u0r = v[(0 * 3 + c) * 2], u0i = v[(0 * 3 + c) * 2 + 1];
+    const R u1r = v[(1 * 3 + c) * 2], u1i = v[(1 * 3 + c) * 2 + 1];
+    const R l0r = v[(2 * 3 + c) * 2], l0i = v[(2 * 3 + c) * 2 + 1];
+    const R l1r = v[(3 * 3 + c) * 2], l1i = v[(3 * 3 + c) * 2 + 1];
+    R h0r, h0i, h1r, h1i;
+    if (MU == 0) {  // B l = (-i l1, -i l0)
+      h0r = u0r - SGN * l1i; h0i = u0i + SGN * l1r;
+      h1r = u1r - SGN * l0i; h1i = u1i + SGN * l0r;
+    } else if (MU == 1) {  // B l = (-l1, l0)
+      h0r = u0r + SGN * l1r; h0i = u0i + SGN * l1i;
+      h1r = u1r - SGN * l0r; h1i = u1i - SGN * l0i;
+    } else if (MU == 2) {  // B l = (-i l0, i l1)
+      h0r = u0r - SGN * l0i; h0i = u0i + SGN * l0r;
+      h1r = u1r + SGN * l1i; h1i = u1i - SGN * l1r;
+    } else {  // B l = l
+      h0r = u0r - SGN * l0r; h0i = u0i - SGN * l0i;
+      h1r = u1r - SGN * l1r; h1i = u1i - SGN * l1i;
+    }
+    h[(0 * 3 + c) * 2] = h0r; h[(0 * 3 + c) * 2 + 1] = h0i;
+    h[(1 * 3 + c) * 2] = h1r; h[(1 * 3 + c) * 2 + 1] = h1i;
+  }
+}
+
+// w = U h for both spins (U already includes the dagger of backward links)
+template <typename R>
+__device__ inline void link_mul(const R u[18], const R h[12], R w[12]) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      R re = 0, im = 0;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const R ur = u[(a * 3 + b) * 2], ui = u[(a * 3 + b) * 2 + 1];
+        const R hr = h[(k * 3 + b) * 2], hi = h[(k * 3 + b) * 2 + 1];
+        re += ur * hr - ui * hi;
+        im += ur * hi + ui * hr;
+      }
+      w[(k * 3 + a) * 2] = re;
+      w[(k * 3 + a) * 2 + 1] = im;
+    }
+}
+
+// acc += (w, -SGN B^+ w): B_x^+ w = (i w1, i w0), B_y^+ w = (w1, -w0),
+// B_z^+ w = (i w0, -i w1), B_t^+ w = (w0, w1).
+template <int MU, int SGN, typename R>
+__device__ inline void accumulate(R acc[24], const R w[12]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const R w0r = w[(0 * 3 + c) * 2], w0i = w[(0 * 3 + c) * 2 + 1];
+    const R w1r = w[(1 * 3 + c) * 2], w1i = w[(1 * 3 + c) * 2 + 1];
+    acc[(0 * 3 + c) * 2] += w0r; acc[(0 * 3 + c) * 2 + 1] += w0i;
+    acc[(1 * 3 + c) * 2] += w1r; acc[(1 * 3 + c) * 2 + 1] += w1i;
+    R l0r, l0i, l1r, l1i;  // -SGN B^+ w
+    if (MU == 0) {
+      l0r = SGN * w1i; l0i = -SGN * w1r;
+      l1r = SGN * w0i; l1i = -SGN * w0r;
+    } else if (MU == 1) {
+      l0r = -SGN * w1r; l0i = -SGN * w1i;
+      l1r = SGN * w0r; l1i = SGN * w0i;
+    } else if (MU == 2) {
+      l0r = SGN * w0i; l0i = -SGN * w0r;
+      l1r = -SGN * w1i; l1i = SGN * w1r;
+    } else {
+      l0r = -SGN * w0r; l0i = -SGN * w0i;
+      l1r = -SGN * w1r; l1i = -SGN * w1i;
+    }
+    acc[(2 * 3 + c) * 2] += l0r; acc[(2 * 3 + c) * 2 + 1] += l0i;
+    acc[(3 * 3 + c) * 2] += l1r; acc[(3 * 3 + c) * 2 + 1] += l1i;
+  }
+}
+
+}  // namespace mspcg

@@ -1,0 +1,129 @@
+// Host-side declarations shared by the kernel and API translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/mspcg.h"
+
+namespace mspcg {
+
+// Epilogues of the hop kernel (what is written for each output 5D site):
+enum Epi {
+  EPI_SCALE = 0,          // out = scale * hop
+  EPI_DENSE = 1,          // out = scale * X hop, X a real Ls x Ls matrix per chirality
+  EPI_MPHIDAG = 2,        // out = scale * M_phi^+ hop
+  EPI_M5_OTHER = 3,       // out = M_5 other + scale * hop
+  EPI_M5DAG_MPHIDAG = 4,  // out = M_5^+ other + scale * M_phi^+ hop
+};
+
+// A field stored as [rhs][site][s][24] over a list of `stride` sites.
+struct Vec {
+  void *data = nullptr;
+  float *norm = nullptr;  // F16/BF16 only: [rhs][site][s]
+  int prec = MSPCG_F64;
+  long long stride = 0;   // sites per right-hand side
+};
+
+struct HopArgs {
+  int nsites;          // output list length
+  int Ls, nrhs, nsite_wg;
+  const int *site_cb;  // [nsites] cb of the output site in the full lattice (-1: padding)
+  const int *nbr;      // [nsites][8] input-list index of neighbour d = 2 mu + (0 fwd, 1 bwd), -1: zero
+  const void *in;
+  const float *in_norm;
+  long long in_stride;
+  void *out;
+  float *out_norm;
+  long long out_stride;
+  const void *links;   // [cb][8][18] for the output parity; sign of the time boundary folded in
+  const void *other;   // EPI_M5_OTHER / EPI_M5DAG_MPHIDAG operand
+  const float *other_norm;
+  long long other_stride;
+  const int *other_idx;  // output site -> index in `other` (-1: zero); nullptr: identity
+  double scale;
+  const double *mat;   // EPI_DENSE: [2][Ls][Ls] row-major (chirality +, then -)
+  double mphi_b, mphi_c, mf, m5_alpha, m5_beta;
+  double *partial;     // DOT: [gridDim.x][nrhs] partial sums of Re<w, out>
+  const void *dotw;
+  const float *dotw_norm;
+  long long dotw_stride;
+};
+
+// Launch the hop kernel for storage `prec`; returns hipSuccess or the launch error.
+hipError_t launch_hop(int prec, int dagger, int pre_mphi, int epi, int dot, const HopArgs &a, hipStream_t st);
+
+// out = X in on a site list (identity list), X = a + b P_chi (dag: P_chi^+) or a dense chiral matrix.
+struct Op5Args {
+  int nsites, Ls, nrhs, nsite_wg;
+  const void *in;
+  const float *in_norm;
+  void *out;
+  float *out_norm;
+  long long stride;
+  int dense;            // 1: use mat; 0: a + b P_chi
+  const double *mat;    // [2][Ls][Ls]
+  double a, b, mf;
+  int dag;
+};
+hipError_t launch_op5(int prec, const Op5Args &a, hipStream_t st);
+
+// Precision conversion of [rhs][site][s][24] fields.
+hipError_t launch_convert(const Vec &out, const Vec &in, int nrhs, long long nsites5, hipStream_t st);
+
+// ------------------------------------------------------------- FP64 BLAS (outer solver)
+// n = reals per right-hand side; vectors are [nrhs][n] doubles.
+constexpr int kBlasWG = 256;
+constexpr int kBlasGrid = 512;  // workgroups per right-hand side (fixed: deterministic sums)
+hipError_t blas_dot_partial(const double *a, const double *b, long long n, int nrhs, double *partial, hipStream_t st);
+hipError_t blas_reduce(const double *partial, int nparts, int nrhs, double *out, hipStream_t st);
+// x += alpha p, r -= alpha q, partial |r|^2; alpha[r] read from scal
+hipError_t blas_update_xr(double *x, double *r, const double *p, const double *q, const double *alpha, long long n,
+                          int nrhs, double *partial, hipStream_t st);
+// p = z + beta p
+hipError_t blas_xpay(double *p, const double *z, const double *beta, long long n, int nrhs, hipStream_t st);
+// out = a x + b y (host scalars)
+hipError_t blas_axpby(double *out, double a, const double *x, double b, const double *y, long long n, int nrhs,
+                      hipStream_t st);
+// Solver scalars per right-hand side (all device arrays [nrhs]):
+//   mode 0: alpha = active ? rho / pap : 0
+//   mode 1: beta = active ? rho_new / rho : 0; rho = rho_new
+hipError_t solver_scalars(int mode, int nrhs, const int *active, double *rho, const double *x1, double *out,
+                          hipStream_t st);
+
+// ------------------------------------------------------------- block preconditioner
+struct BlockArgs {
+  int nsites;         // B_e list length (padded)
+  int Ls, nrhs, nsite_wg;
+  const int *be_cb;   // [nsites]
+  const int *be_blk;  // [nsites] block of the site (-1: padding)
+  int nblocks;
+  const int *be_off;  // [nblocks+1] padded offsets (multiples of 64)
+};
+// r_s = p_s = scale * r(cb), x_s = 0; partial |r_s|^2 per workgroup.  scale = sqrt(n_total/rr[rhs]).
+hipError_t block_gather(int prec, const BlockArgs &b, const Vec &xs, const Vec &rs, const Vec &ps, const Vec &rglob,
+                        const double *rr, double n_total, double *partial, hipStream_t st);
+// z(cb) = x_s / scale; partial Re<z, r> per workgroup (FP64 r, z)
+hipError_t block_scatter(int prec, const BlockArgs &b, const Vec &zglob, const Vec &xs, const Vec &rglob,
+                         const double *rr, double n_total, double *partial, hipStream_t st);
+// per (block, rhs): mode 0: alpha = rho/sum(partials) (0 if degenerate)
+//                   mode 1: rho_new = sum; beta = rho_new/rho (0 if rho = 0); rho = rho_new
+//                   mode 2: rho = sum (initialisation)
+hipError_t block_scalars(int mode, const BlockArgs &b, const double *partial, double *scal, hipStream_t st);
+// x += alpha p, r -= alpha Ap, partial |r|^2
+hipError_t block_update_xr(int prec, const BlockArgs &b, const Vec &x, const Vec &r, const Vec &p, const Vec &Ap,
+                           const double *scal, double *partial, hipStream_t st);
+// p = r + beta p
+hipError_t block_update_p(int prec, const BlockArgs &b, const Vec &p, const Vec &r, const double *scal,
+                          hipStream_t st);
+
+// scal layout per (block, rhs): [rho, alpha, beta, pad]
+constexpr int kScal = 4;
+
+// Pack the physical FP64 gauge field [lex][mu][3][3] into per-parity site-packed
+// links [cb][8][18] (forward U_mu(x), backward U_mu(x-mu)^+, time boundary sign folded).
+hipError_t pack_links(int prec, void *out, const double *gauge, const int *lex_of_cb, const int *nbr_lex, int parity,
+                      int Vh, int Lt, int Lxyz, double tbc, hipStream_t st);
+
+}  // namespace mspcg

@@ -1,0 +1,713 @@
+// HIP kernels for gfx950: the Ls-fused Wilson hop with fused fifth-dimension
+// epilogues, fifth-dimension operators, FP64 BLAS for the outer solver and the
+// batched block-CG kernels of the preconditioner.
+//
+// Thread layout of every site kernel: a workgroup owns `nsite_wg` 4D sites of
+// a site list; its threads are (site, rhs, s) with s fastest, so one 4D site's
+// Ls x nrhs spinors are handled by consecutive lanes (coalesced loads of the
+// [rhs][site][s][24] layout, one broadcast link load per direction) and the
+// fifth-dimension coupling is an exchange between neighbouring lanes through LDS.
+#include <algorithm>
+#include <type_traits>
+
+#include "common.h"
+#include "internal.h"
+
+namespace mspcg {
+
+// ---------------------------------------------------------------- helpers
+template <typename R>
+__device__ inline void zero24(R v[24]) {
+#pragma unroll
+  for (int k = 0; k < 24; ++k) v[k] = 0;
+}
+
+// v <- a v + b P_chi v (dag = 0) or a v + b P_chi^+ v (dag = 1) on the Ls column
+// held one s per lane.  P_chi = P- S+ + P+ S-: chirality + (reals 0..11) takes
+// s-1, chirality - (reals 12..23) takes s+1, with the -mf corner.  LDS is
+// structure-of-arrays [24][nthr] so lane-consecutive accesses are conflict free.
+template <typename R>
+__device__ inline void pchi_comb(R *lds, int nthr, int tid, int s, int Ls, R a, R b, R mf, int dag, R v[24]) {
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 24; ++k) lds[k * nthr + tid] = v[k];
+  __syncthreads();
+  const int tm = (s > 0) ? tid - 1 : tid + Ls - 1;
+  const int tp = (s < Ls - 1) ? tid + 1 : tid - (Ls - 1);
+  const R cm = (s > 0) ? R(1) : -mf;
+  const R cp = (s < Ls - 1) ? R(1) : -mf;
+  const int tu = dag ? tp : tm;
+  const int tl = dag ? tm : tp;
+  const R cu = b * (dag ? cp : cm);
+  const R cl = b * (dag ? cm : cp);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) v[k] = a * v[k] + cu * lds[k * nthr + tu];
+#pragma unroll
+  for (int k = 12; k < 24; ++k) v[k] = a * v[k] + cl * lds[k * nthr + tl];
+}
+
+// v <- X v with X real Ls x Ls per chirality (matT[chi][t][s] in LDS, transposed).
+template <typename R>
+__device__ inline void dense_chiral(R *lds, const R *matT, int nthr, int tid, int s, int Ls, R scale, R v[24]) {
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 24; ++k) lds[k * nthr + tid] = v[k];
+  __syncthreads();
+  const int g0 = tid - s;
+  R o[24];
+  zero24(o);
+  for (int t = 0; t < Ls; ++t) {
+    const R mp = matT[t * Ls + s];
+    const R mm = matT[Ls * Ls + t * Ls + s];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) o[k] += mp * lds[k * nthr + g0 + t];
+#pragma unroll
+    for (int k = 12; k < 24; ++k) o[k] += mm * lds[k * nthr + g0 + t];
+  }
+#pragma unroll
+  for (int k = 0; k < 24; ++k) v[k] = scale * o[k];
+}
+
+// Workgroup sum of `val` per right-hand side into partial[blockIdx.x * nrhs + r]
+// (fixed order: deterministic).  Uses the LDS region as doubles.
+__device__ inline void wg_partial(double *ldsd, int nthr, int tid, int Ls, int nrhs, int nsite_wg, double val,
+                                  double *partial) {
+  __syncthreads();
+  ldsd[tid] = val;
+  __syncthreads();
+  const int ngroups = nsite_wg * nrhs;
+  if (tid < ngroups) {
+    double acc = 0;
+    for (int s = 0; s < Ls; ++s) acc += ldsd[tid * Ls + s];
+    ldsd[nthr + tid] = acc;
+  }
+  __syncthreads();
+  if (tid < nrhs) {
+    double acc = 0;
+    for (int g = 0; g < nsite_wg; ++g) acc += ldsd[nthr + g * nrhs + tid];
+    partial[(size_t)blockIdx.x * nrhs + tid] = acc;
+  }
+}
+
+// ---------------------------------------------------------------- the hop kernel
+// out(x) = epilogue( sum_mu [ P^{SGN_f}_mu U_mu(x) phi(x+mu) + P^{SGN_b}_mu U_mu(x-mu)^+ phi(x-mu) ] )
+// with phi = M_phi in (PRE) or in; SGN_f = +1, SGN_b = -1 for H and the reverse
+// for the daggered hop g5 H g5 = H^+.
+template <typename S, int DAG, int PRE, int EPI, int DOT>
+__global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
+  using R = typename Traits<S>::R;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nthr = blockDim.x;
+  R *lds = reinterpret_cast<R *>(smem);
+  R *matT = lds + 24 * nthr;
+  const int tid = threadIdx.x;
+  const int Ls = a.Ls;
+  const int G = a.nrhs * Ls;
+  const int sl = tid / G;
+  const int rem = tid - sl * G;
+  const int r = rem / Ls;
+  const int s = rem - r * Ls;
+  const int site = blockIdx.x * a.nsite_wg + sl;
+  const int cb = (site < a.nsites) ? a.site_cb[site] : -1;
+  const bool active = cb >= 0;
+
+  if (EPI == EPI_DENSE) {
+    for (int i = tid; i < 2 * Ls * Ls; i += nthr) {
+      const int chi = i / (Ls * Ls), t = (i / Ls) % Ls, so = i % Ls;  // matT[chi][t][so] = mat[chi][so][t]
+      matT[i] = (R)a.mat[chi * Ls * Ls + so * Ls + t];
+    }
+  }
+
+  const S *in = reinterpret_cast<const S *>(a.in);
+  const S *links = reinterpret_cast<const S *>(a.links);
+  R acc[24];
+  zero24(acc);
+
+#pragma unroll
+  for (int d = 0; d < 8; ++d) {
+    const int j = active ? a.nbr[(size_t)site * 8 + d] : -1;
+    R v[24];
+    if (j >= 0)
+      load24<R>(in, a.in_norm, ((size_t)r * a.in_stride + j) * Ls + s, v);
+    else
+      zero24(v);
+    if (PRE) pchi_comb<R>(lds, nthr, tid, s, Ls, (R)a.mphi_b, (R)a.mphi_c, (R)a.mf, 0, v);
+    if (j >= 0) {
+      R u[18], h[12], w[12];
+      load18<R>(links, (size_t)cb * 8 + d, u);
+      const int mu = d >> 1;
+      const bool bw = d & 1;
+      // SGN = +1 selects (1 - g_mu): forward for H, backward for H^+
+      const bool plus = (bw == (DAG != 0));
+      if (mu == 0) {
+        if (plus) { project<0, 1>(v, h); link_mul(u, h, w); accumulate<0, 1>(acc, w); }
+        else      { project<0, -1>(v, h); link_mul(u, h, w); accumulate<0, -1>(acc, w); }
+      } else if (mu == 1) {
+        if (plus) { project<1, 1>(v, h); link_mul(u, h, w); accumulate<1, 1>(acc, w); }
+        else      { project<1, -1>(v, h); link_mul(u, h, w); accumulate<1, -1>(acc, w); }
+      } else if (mu == 2) {
+        if (plus) { project<2, 1>(v, h); link_mul(u, h, w); accumulate<2, 1>(acc, w); }
+        else      { project<2, -1>(v, h); link_mul(u, h, w); accumulate<2, -1>(acc, w); }
+      } else {
+        if (plus) { project<3, 1>(v, h); link_mul(u, h, w); accumulate<3, 1>(acc, w); }
+        else      { project<3, -1>(v, h); link_mul(u, h, w); accumulate<3, -1>(acc, w); }
+      }
+    }
+  }
+
+  const R scale = (R)a.scale;
+  if (EPI == EPI_SCALE) {
+#pragma unroll
+    for (int k = 0; k < 24; ++k) acc[k] *= scale;
+  } else if (EPI == EPI_DENSE) {
+    dense_chiral<R>(lds, matT, nthr, tid, s, Ls, scale, acc);
+  } else if (EPI == EPI_MPHIDAG || EPI == EPI_M5DAG_MPHIDAG) {
+    pchi_comb<R>(lds, nthr, tid, s, Ls, (R)a.mphi_b, (R)a.mphi_c, (R)a.mf, 1, acc);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) acc[k] *= scale;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 24; ++k) acc[k] *= scale;
+  }
+  if (EPI == EPI_M5_OTHER || EPI == EPI_M5DAG_MPHIDAG) {
+    const int oi = active ? (a.other_idx ? a.other_idx[site] : site) : -1;
+    R o[24];
+    if (oi >= 0)
+      load24<R>(reinterpret_cast<const S *>(a.other), a.other_norm, ((size_t)r * a.other_stride + oi) * Ls + s, o);
+    else
+      zero24(o);
+    // M_5 = alpha - beta P_chi ; M_5^+ = alpha - beta P_chi^+
+    pchi_comb<R>(lds, nthr, tid, s, Ls, (R)a.m5_alpha, (R)(-a.m5_beta), (R)a.mf, EPI == EPI_M5DAG_MPHIDAG, o);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) acc[k] += o[k];
+  }
+
+  if (active) store24<R>(reinterpret_cast<S *>(a.out), a.out_norm, ((size_t)r * a.out_stride + site) * Ls + s, acc);
+
+  if (DOT) {
+    double val = 0;
+    if (active) {
+      R w[24];
+      load24<R>(reinterpret_cast<const S *>(a.dotw), a.dotw_norm, ((size_t)r * a.dotw_stride + site) * Ls + s, w);
+      R t = 0;
+#pragma unroll
+      for (int k = 0; k < 24; ++k) t += w[k] * acc[k];
+      val = (double)t;
+    }
+    wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, a.nrhs, a.nsite_wg, val, a.partial);
+  }
+}
+
+template <typename S>
+static size_t hop_lds_bytes(const HopArgs &a, int nthr, int epi, int dot) {
+  using R = typename Traits<S>::R;
+  size_t b = (size_t)24 * nthr * sizeof(R);
+  if (epi == EPI_DENSE) b += (size_t)2 * a.Ls * a.Ls * sizeof(R);
+  if (dot) b = std::max(b, (size_t)2 * nthr * sizeof(double));
+  return b;
+}
+
+template <typename S, int DAG, int PRE, int EPI, int DOT>
+static hipError_t launch_hop_t(const HopArgs &a, hipStream_t st) {
+  const int nthr = a.nsite_wg * a.nrhs * a.Ls;
+  const int grid = (a.nsites + a.nsite_wg - 1) / a.nsite_wg;
+  if (nthr < 1 || nthr > 256 || grid < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((hop_kernel<S, DAG, PRE, EPI, DOT>), dim3(grid), dim3(nthr), hop_lds_bytes<S>(a, nthr, EPI, DOT),
+                     st, a);
+  return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t dispatch_hop(int dagger, int pre, int epi, int dot, const HopArgs &a, hipStream_t st) {
+  // the combinations used by the operators (anything else is rejected)
+#define MSPCG_HOP(D, P, E, T) \
+  if (dagger == D && pre == P && epi == E && dot == T) return launch_hop_t<S, D, P, E, T>(a, st);
+  MSPCG_HOP(0, 1, EPI_SCALE, 0)          // M^4 in
+  MSPCG_HOP(1, 0, EPI_MPHIDAG, 0)        // (M^4)^+ in
+  MSPCG_HOP(0, 1, EPI_DENSE, 0)          // M_phi M_5^-1 M^4 in (first hop of D_PC)
+  MSPCG_HOP(0, 0, EPI_M5_OTHER, 0)       // M_5 psi + 1/2 H c
+  MSPCG_HOP(1, 0, EPI_DENSE, 0)          // M_5^-+ (M^4)^+ y
+  MSPCG_HOP(1, 0, EPI_M5DAG_MPHIDAG, 0)  // M_5^+ y + 1/2 M_phi^+ H^+ f
+  MSPCG_HOP(1, 0, EPI_M5DAG_MPHIDAG, 1)  //   ... with the fused <w, out>
+  MSPCG_HOP(0, 1, EPI_DENSE, 1)
+#undef MSPCG_HOP
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_hop(int prec, int dagger, int pre, int epi, int dot, const HopArgs &a, hipStream_t st) {
+  switch (prec) {
+    case MSPCG_F64: return dispatch_hop<double>(dagger, pre, epi, dot, a, st);
+    case MSPCG_F32: return dispatch_hop<float>(dagger, pre, epi, dot, a, st);
+    case MSPCG_F16: return dispatch_hop<_Float16>(dagger, pre, epi, dot, a, st);
+    case MSPCG_BF16: return dispatch_hop<bf16>(dagger, pre, epi, dot, a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- fifth-dimension operator
+template <typename S>
+__global__ void __launch_bounds__(256) op5_kernel(const Op5Args a) {
+  using R = typename Traits<S>::R;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nthr = blockDim.x;
+  R *lds = reinterpret_cast<R *>(smem);
+  R *matT = lds + 24 * nthr;
+  const int tid = threadIdx.x, Ls = a.Ls, G = a.nrhs * Ls;
+  const int sl = tid / G, rem = tid - sl * G, r = rem / Ls, s = rem - r * Ls;
+  const int site = blockIdx.x * a.nsite_wg + sl;
+  const bool active = site < a.nsites;
+  if (a.dense)
+    for (int i = tid; i < 2 * Ls * Ls; i += nthr) {
+      const int chi = i / (Ls * Ls), t = (i / Ls) % Ls, so = i % Ls;
+      matT[i] = (R)a.mat[chi * Ls * Ls + so * Ls + t];
+    }
+  R v[24];
+  const size_t idx = ((size_t)r * a.stride + site) * Ls + s;
+  if (active)
+    load24<R>(reinterpret_cast<const S *>(a.in), a.in_norm, idx, v);
+  else
+    zero24(v);
+  if (a.dense)
+    dense_chiral<R>(lds, matT, nthr, tid, s, Ls, R(1), v);
+  else
+    pchi_comb<R>(lds, nthr, tid, s, Ls, (R)a.a, (R)a.b, (R)a.mf, a.dag, v);
+  if (active) store24<R>(reinterpret_cast<S *>(a.out), a.out_norm, idx, v);
+}
+
+hipError_t launch_op5(int prec, const Op5Args &a, hipStream_t st) {
+  const int nthr = a.nsite_wg * a.nrhs * a.Ls;
+  const int grid = (a.nsites + a.nsite_wg - 1) / a.nsite_wg;
+  if (nthr < 1 || nthr > 256 || grid < 1) return hipErrorInvalidValue;
+  const size_t rsz = (prec == MSPCG_F64) ? 8 : 4;
+  const size_t lds = (24 * (size_t)nthr + 2 * (size_t)a.Ls * a.Ls) * rsz;
+  switch (prec) {
+    case MSPCG_F64: hipLaunchKernelGGL(op5_kernel<double>, dim3(grid), dim3(nthr), lds, st, a); break;
+    case MSPCG_F32: hipLaunchKernelGGL(op5_kernel<float>, dim3(grid), dim3(nthr), lds, st, a); break;
+    case MSPCG_F16: hipLaunchKernelGGL(op5_kernel<_Float16>, dim3(grid), dim3(nthr), lds, st, a); break;
+    case MSPCG_BF16: hipLaunchKernelGGL(op5_kernel<bf16>, dim3(grid), dim3(nthr), lds, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- conversion
+template <typename SO, typename SI>
+__global__ void convert_kernel(SO *out, float *out_norm, const SI *in, const float *in_norm, long long n5) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n5) return;
+  float v[24];
+  if (sizeof(SI) == 8) {
+    double t[24];
+    load24<double>(reinterpret_cast<const double *>(in), in_norm, i, t);
+    if (sizeof(SO) == 8) {
+      store24<double>(reinterpret_cast<double *>(out), out_norm, i, t);
+      return;
+    }
+#pragma unroll
+    for (int k = 0; k < 24; ++k) v[k] = (float)t[k];
+  } else {
+    load24<float>(in, in_norm, i, v);
+  }
+  if (sizeof(SO) == 8) {
+    double t[24];
+#pragma unroll
+    for (int k = 0; k < 24; ++k) t[k] = v[k];
+    store24<double>(reinterpret_cast<double *>(out), out_norm, i, t);
+  } else {
+    store24<float>(out, out_norm, i, v);
+  }
+}
+
+template <typename SO>
+static hipError_t convert_from(const Vec &out, const Vec &in, long long n5, hipStream_t st) {
+  const int blk = 256;
+  const long long grid = (n5 + blk - 1) / blk;
+  SO *o = reinterpret_cast<SO *>(out.data);
+  switch (in.prec) {
+    case MSPCG_F64: hipLaunchKernelGGL((convert_kernel<SO, double>), dim3(grid), dim3(blk), 0, st, o, out.norm, (const double *)in.data, in.norm, n5); break;
+    case MSPCG_F32: hipLaunchKernelGGL((convert_kernel<SO, float>), dim3(grid), dim3(blk), 0, st, o, out.norm, (const float *)in.data, in.norm, n5); break;
+    case MSPCG_F16: hipLaunchKernelGGL((convert_kernel<SO, _Float16>), dim3(grid), dim3(blk), 0, st, o, out.norm, (const _Float16 *)in.data, in.norm, n5); break;
+    case MSPCG_BF16: hipLaunchKernelGGL((convert_kernel<SO, bf16>), dim3(grid), dim3(blk), 0, st, o, out.norm, (const bf16 *)in.data, in.norm, n5); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(const Vec &out, const Vec &in, int nrhs, long long nsites5, hipStream_t st) {
+  const long long n5 = nsites5 * nrhs;
+  if (n5 <= 0) return hipSuccess;
+  switch (out.prec) {
+    case MSPCG_F64: return convert_from<double>(out, in, n5, st);
+    case MSPCG_F32: return convert_from<float>(out, in, n5, st);
+    case MSPCG_F16: return convert_from<_Float16>(out, in, n5, st);
+    case MSPCG_BF16: return convert_from<bf16>(out, in, n5, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- FP64 BLAS
+// Grid (kBlasGrid, nrhs) with a grid-stride loop over double2 pairs: the set
+// of elements each thread sums, and the reduction tree, depend only on n.
+__device__ inline void block_sum_store(double v, double *out) {
+  __shared__ double sh[kBlasWG];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kBlasWG / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+__global__ void __launch_bounds__(kBlasWG) k_dot(const double *a, const double *b, long long n, double *partial) {
+  const int r = blockIdx.y;
+  const double2 *x = reinterpret_cast<const double2 *>(a + (size_t)r * n);
+  const double2 *y = reinterpret_cast<const double2 *>(b + (size_t)r * n);
+  const long long n2 = n / 2;
+  double acc = 0;
+  for (long long i = (long long)blockIdx.x * kBlasWG + threadIdx.x; i < n2; i += (long long)kBlasGrid * kBlasWG) {
+    const double2 u = x[i], v = y[i];
+    acc += u.x * v.x + u.y * v.y;
+  }
+  block_sum_store(acc, partial + (size_t)blockIdx.x * gridDim.y + r);
+}
+
+hipError_t blas_dot_partial(const double *a, const double *b, long long n, int nrhs, double *partial, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot, dim3(kBlasGrid, nrhs), dim3(kBlasWG), 0, st, a, b, n, partial);
+  return hipGetLastError();
+}
+
+// partial[p][r] -> out[r]; one workgroup per right-hand side
+__global__ void __launch_bounds__(kBlasWG) k_reduce(const double *partial, int nparts, int nrhs, double *out) {
+  const int r = blockIdx.x;
+  double acc = 0;
+  for (int p = threadIdx.x; p < nparts; p += kBlasWG) acc += partial[(size_t)p * nrhs + r];
+  block_sum_store(acc, out + r);
+}
+
+hipError_t blas_reduce(const double *partial, int nparts, int nrhs, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(nrhs), dim3(kBlasWG), 0, st, partial, nparts, nrhs, out);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kBlasWG) k_update_xr(double *xv, double *rv, const double *pv, const double *qv,
+                                                       const double *alpha, long long n, double *partial) {
+  const int r = blockIdx.y;
+  const double al = alpha[r];
+  double2 *x = reinterpret_cast<double2 *>(xv + (size_t)r * n);
+  double2 *rr = reinterpret_cast<double2 *>(rv + (size_t)r * n);
+  const double2 *p = reinterpret_cast<const double2 *>(pv + (size_t)r * n);
+  const double2 *q = reinterpret_cast<const double2 *>(qv + (size_t)r * n);
+  const long long n2 = n / 2;
+  double acc = 0;
+  for (long long i = (long long)blockIdx.x * kBlasWG + threadIdx.x; i < n2; i += (long long)kBlasGrid * kBlasWG) {
+    double2 xi = x[i], ri = rr[i];
+    const double2 pi = p[i], qi = q[i];
+    xi.x += al * pi.x; xi.y += al * pi.y;
+    ri.x -= al * qi.x; ri.y -= al * qi.y;
+    x[i] = xi;
+    rr[i] = ri;
+    acc += ri.x * ri.x + ri.y * ri.y;
+  }
+  block_sum_store(acc, partial + (size_t)blockIdx.x * gridDim.y + r);
+}
+
+hipError_t blas_update_xr(double *x, double *r, const double *p, const double *q, const double *alpha, long long n,
+                          int nrhs, double *partial, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_xr, dim3(kBlasGrid, nrhs), dim3(kBlasWG), 0, st, x, r, p, q, alpha, n, partial);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kBlasWG) k_xpay(double *pv, const double *zv, const double *beta, long long n) {
+  const int r = blockIdx.y;
+  const double be = beta[r];
+  double2 *p = reinterpret_cast<double2 *>(pv + (size_t)r * n);
+  const double2 *z = reinterpret_cast<const double2 *>(zv + (size_t)r * n);
+  const long long n2 = n / 2;
+  for (long long i = (long long)blockIdx.x * kBlasWG + threadIdx.x; i < n2; i += (long long)kBlasGrid * kBlasWG) {
+    double2 pi = p[i];
+    const double2 zi = z[i];
+    pi.x = zi.x + be * pi.x;
+    pi.y = zi.y + be * pi.y;
+    p[i] = pi;
+  }
+}
+
+hipError_t blas_xpay(double *p, const double *z, const double *beta, long long n, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_xpay, dim3(kBlasGrid, nrhs), dim3(kBlasWG), 0, st, p, z, beta, n);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kBlasWG) k_axpby(double *ov, double a, const double *xv, double b, const double *yv,
+                                                   long long n) {
+  const int r = blockIdx.y;
+  double2 *o = reinterpret_cast<double2 *>(ov + (size_t)r * n);
+  const double2 *x = reinterpret_cast<const double2 *>(xv + (size_t)r * n);
+  const double2 *y = reinterpret_cast<const double2 *>(yv + (size_t)r * n);
+  const long long n2 = n / 2;
+  for (long long i = (long long)blockIdx.x * kBlasWG + threadIdx.x; i < n2; i += (long long)kBlasGrid * kBlasWG) {
+    const double2 xi = x[i], yi = y[i];
+    o[i] = make_double2(a * xi.x + b * yi.x, a * xi.y + b * yi.y);
+  }
+}
+
+hipError_t blas_axpby(double *out, double a, const double *x, double b, const double *y, long long n, int nrhs,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_axpby, dim3(kBlasGrid, nrhs), dim3(kBlasWG), 0, st, out, a, x, b, y, n);
+  return hipGetLastError();
+}
+
+__global__ void k_solver_scalars(int mode, int nrhs, const int *active, double *rho, const double *x1, double *out) {
+  const int r = threadIdx.x;
+  if (r >= nrhs) return;
+  const bool on = active[r] != 0;
+  if (mode == 0) {
+    const double pap = x1[r];
+    out[r] = (on && pap != 0.0) ? rho[r] / pap : 0.0;
+  } else {
+    const double rn = x1[r];
+    out[r] = (on && rho[r] != 0.0) ? rn / rho[r] : 0.0;
+    if (on) rho[r] = rn;
+  }
+}
+
+hipError_t solver_scalars(int mode, int nrhs, const int *active, double *rho, const double *x1, double *out,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_solver_scalars, dim3(1), dim3(64), 0, st, mode, nrhs, active, rho, x1, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- block preconditioner
+// The B_e list is ordered block by block, each block padded to a multiple of
+// 64 sites, so with nsite_wg dividing 64 every workgroup lies in one block.
+template <typename S>
+__global__ void __launch_bounds__(256) k_block_gather(const BlockArgs b, Vec xs, Vec rs, Vec ps, const double *rg,
+                                                       long long rg_stride, const double *rr, double n_total,
+                                                       double *partial) {
+  using R = typename Traits<S>::R;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nthr = blockDim.x, tid = threadIdx.x, Ls = b.Ls, G = b.nrhs * Ls;
+  const int sl = tid / G, rem = tid - sl * G, r = rem / Ls, s = rem - r * Ls;
+  const int site = blockIdx.x * b.nsite_wg + sl;
+  const int cb = site < b.nsites ? b.be_cb[site] : -1;
+  double val = 0;
+  if (cb >= 0) {
+    const double scale = rr ? (rr[r] > 0 ? sqrt(n_total / rr[r]) : 0.0) : 1.0;
+    double t[24];
+    load24<double>(rg, nullptr, ((size_t)r * rg_stride + cb) * Ls + s, t);
+    R v[24];
+#pragma unroll
+    for (int k = 0; k < 24; ++k) v[k] = (R)(scale * t[k]);
+    const size_t o = ((size_t)r * rs.stride + site) * Ls + s;
+    store24<R>(reinterpret_cast<S *>(rs.data), rs.norm, o, v);
+    // read back what was stored so that r and p start identical and the sum matches them
+    load24<R>(reinterpret_cast<const S *>(rs.data), rs.norm, o, v);
+    store24<R>(reinterpret_cast<S *>(ps.data), ps.norm, o, v);
+    R z[24];
+    zero24(z);
+    store24<R>(reinterpret_cast<S *>(xs.data), xs.norm, o, z);
+    R acc = 0;
+#pragma unroll
+    for (int k = 0; k < 24; ++k) acc += v[k] * v[k];
+    val = (double)acc;
+  }
+  wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, b.nrhs, b.nsite_wg, val, partial);
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_block_scatter(const BlockArgs b, double *zg, long long zg_stride, Vec xs,
+                                                        const double *rg, const double *rr, double n_total,
+                                                        double *partial) {
+  using R = typename Traits<S>::R;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nthr = blockDim.x, tid = threadIdx.x, Ls = b.Ls, G = b.nrhs * Ls;
+  const int sl = tid / G, rem = tid - sl * G, r = rem / Ls, s = rem - r * Ls;
+  const int site = blockIdx.x * b.nsite_wg + sl;
+  const int cb = site < b.nsites ? b.be_cb[site] : -1;
+  double val = 0;
+  if (cb >= 0) {
+    const double inv = rr ? (rr[r] > 0 ? sqrt(rr[r] / n_total) : 0.0) : 1.0;
+    R v[24];
+    load24<R>(reinterpret_cast<const S *>(xs.data), xs.norm, ((size_t)r * xs.stride + site) * Ls + s, v);
+    double z[24], t[24];
+#pragma unroll
+    for (int k = 0; k < 24; ++k) z[k] = inv * (double)v[k];
+    const size_t g = ((size_t)r * zg_stride + cb) * Ls + s;
+    store24<double>(zg, nullptr, g, z);
+    if (rg) {
+      load24<double>(rg, nullptr, g, t);
+#pragma unroll
+      for (int k = 0; k < 24; ++k) val += z[k] * t[k];
+    }
+  }
+  wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, b.nrhs, b.nsite_wg, val, partial);
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_block_update_xr(const BlockArgs b, Vec xv, Vec rv, Vec pv, Vec qv,
+                                                          const double *scal, double *partial) {
+  using R = typename Traits<S>::R;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nthr = blockDim.x, tid = threadIdx.x, Ls = b.Ls, G = b.nrhs * Ls;
+  const int sl = tid / G, rem = tid - sl * G, r = rem / Ls, s = rem - r * Ls;
+  const int site = blockIdx.x * b.nsite_wg + sl;
+  const int blk = site < b.nsites ? b.be_blk[site] : -1;
+  double val = 0;
+  if (blk >= 0) {
+    const R al = (R)scal[((size_t)blk * b.nrhs + r) * kScal + 1];
+    const size_t o = ((size_t)r * xv.stride + site) * Ls + s;
+    R x[24], rr[24], p[24], q[24];
+    load24<R>(reinterpret_cast<const S *>(xv.data), xv.norm, o, x);
+    load24<R>(reinterpret_cast<const S *>(rv.data), rv.norm, o, rr);
+    load24<R>(reinterpret_cast<const S *>(pv.data), pv.norm, o, p);
+    load24<R>(reinterpret_cast<const S *>(qv.data), qv.norm, o, q);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) {
+      x[k] += al * p[k];
+      rr[k] -= al * q[k];
+    }
+    store24<R>(reinterpret_cast<S *>(xv.data), xv.norm, o, x);
+    store24<R>(reinterpret_cast<S *>(rv.data), rv.norm, o, rr);
+    // the norm is taken of the stored (rounded) residual
+    load24<R>(reinterpret_cast<const S *>(rv.data), rv.norm, o, rr);
+    R acc = 0;
+#pragma unroll
+    for (int k = 0; k < 24; ++k) acc += rr[k] * rr[k];
+    val = (double)acc;
+  }
+  wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, b.nrhs, b.nsite_wg, val, partial);
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_block_update_p(const BlockArgs b, Vec pv, Vec rv, const double *scal) {
+  using R = typename Traits<S>::R;
+  const int tid = threadIdx.x, Ls = b.Ls, G = b.nrhs * Ls;
+  const int sl = tid / G, rem = tid - sl * G, r = rem / Ls, s = rem - r * Ls;
+  const int site = blockIdx.x * b.nsite_wg + sl;
+  const int blk = site < b.nsites ? b.be_blk[site] : -1;
+  if (blk < 0) return;
+  const R be = (R)scal[((size_t)blk * b.nrhs + r) * kScal + 2];
+  const size_t o = ((size_t)r * pv.stride + site) * Ls + s;
+  R p[24], rr[24];
+  load24<R>(reinterpret_cast<const S *>(pv.data), pv.norm, o, p);
+  load24<R>(reinterpret_cast<const S *>(rv.data), rv.norm, o, rr);
+#pragma unroll
+  for (int k = 0; k < 24; ++k) p[k] = rr[k] + be * p[k];
+  store24<R>(reinterpret_cast<S *>(pv.data), pv.norm, o, p);
+}
+
+// one thread per (block, rhs); sums that block's workgroup partials in order
+__global__ void k_block_scalars(int mode, int nblocks, int nrhs, int nsite_wg, const int *be_off,
+                                const double *partial, double *scal) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nblocks * nrhs) return;
+  const int blk = i / nrhs, r = i % nrhs;
+  const int w0 = be_off[blk] / nsite_wg, w1 = be_off[blk + 1] / nsite_wg;
+  double sum = 0;
+  for (int w = w0; w < w1; ++w) sum += partial[(size_t)w * nrhs + r];
+  double *sc = scal + (size_t)i * kScal;
+  if (mode == 0) {
+    sc[1] = (sum > 0.0 && sc[0] > 0.0) ? sc[0] / sum : 0.0;
+  } else if (mode == 1) {
+    sc[2] = (sc[0] > 0.0) ? sum / sc[0] : 0.0;
+    sc[0] = sum;
+  } else {
+    sc[0] = sum;
+    sc[1] = sc[2] = 0.0;
+  }
+}
+
+static inline int block_threads(const BlockArgs &b) { return b.nsite_wg * b.nrhs * b.Ls; }
+static inline int block_grid(const BlockArgs &b) { return (b.nsites + b.nsite_wg - 1) / b.nsite_wg; }
+static inline size_t block_lds(const BlockArgs &b) { return (size_t)2 * block_threads(b) * sizeof(double); }
+
+#define MSPCG_PREC_SWITCH(prec, CALL)                 \
+  switch (prec) {                                     \
+    case MSPCG_F64: { using S = double; CALL; } break;   \
+    case MSPCG_F32: { using S = float; CALL; } break;    \
+    case MSPCG_F16: { using S = _Float16; CALL; } break; \
+    case MSPCG_BF16: { using S = bf16; CALL; } break;    \
+    default: return hipErrorInvalidValue;             \
+  }
+
+hipError_t block_gather(int prec, const BlockArgs &b, const Vec &xs, const Vec &rs, const Vec &ps, const Vec &rglob,
+                        const double *rr, double n_total, double *partial, hipStream_t st) {
+  if (rglob.prec != MSPCG_F64 || block_threads(b) > 256) return hipErrorInvalidValue;
+  MSPCG_PREC_SWITCH(prec, hipLaunchKernelGGL(k_block_gather<S>, dim3(block_grid(b)), dim3(block_threads(b)),
+                                             block_lds(b), st, b, xs, rs, ps, (const double *)rglob.data,
+                                             rglob.stride, rr, n_total, partial));
+  return hipGetLastError();
+}
+
+hipError_t block_scatter(int prec, const BlockArgs &b, const Vec &zglob, const Vec &xs, const Vec &rglob,
+                         const double *rr, double n_total, double *partial, hipStream_t st) {
+  if (zglob.prec != MSPCG_F64 || block_threads(b) > 256) return hipErrorInvalidValue;
+  MSPCG_PREC_SWITCH(prec, hipLaunchKernelGGL(k_block_scatter<S>, dim3(block_grid(b)), dim3(block_threads(b)),
+                                             block_lds(b), st, b, (double *)zglob.data, zglob.stride, xs,
+                                             (const double *)rglob.data, rr, n_total, partial));
+  return hipGetLastError();
+}
+
+hipError_t block_scalars(int mode, const BlockArgs &b, const double *partial, double *scal, hipStream_t st) {
+  const int n = b.nblocks * b.nrhs;
+  hipLaunchKernelGGL(k_block_scalars, dim3((n + 63) / 64), dim3(64), 0, st, mode, b.nblocks, b.nrhs, b.nsite_wg,
+                     b.be_off, partial, scal);
+  return hipGetLastError();
+}
+
+hipError_t block_update_xr(int prec, const BlockArgs &b, const Vec &x, const Vec &r, const Vec &p, const Vec &Ap,
+                           const double *scal, double *partial, hipStream_t st) {
+  if (block_threads(b) > 256) return hipErrorInvalidValue;
+  MSPCG_PREC_SWITCH(prec, hipLaunchKernelGGL(k_block_update_xr<S>, dim3(block_grid(b)), dim3(block_threads(b)),
+                                             block_lds(b), st, b, x, r, p, Ap, scal, partial));
+  return hipGetLastError();
+}
+
+hipError_t block_update_p(int prec, const BlockArgs &b, const Vec &p, const Vec &r, const double *scal,
+                          hipStream_t st) {
+  if (block_threads(b) > 256) return hipErrorInvalidValue;
+  MSPCG_PREC_SWITCH(prec, hipLaunchKernelGGL(k_block_update_p<S>, dim3(block_grid(b)), dim3(block_threads(b)), 0,
+                                             st, b, p, r, scal));
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- link packing
+template <typename S>
+__global__ void k_pack_links(S *out, const double *gauge, const int *lex_of_cb, const int *nbr_lex, int Vh, int Lt,
+                             int Lxyz, double tbc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // (cb, d)
+  if (i >= Vh * 8) return;
+  const int cb = i >> 3, d = i & 7, mu = d >> 1, bw = d & 1;
+  const int x = lex_of_cb[cb];
+  const int t = x / Lxyz;
+  const int src = bw ? nbr_lex[(size_t)cb * 8 + d] : x;
+  const double sign = (mu == 3 && ((!bw && t == Lt - 1) || (bw && t == 0))) ? tbc : 1.0;
+  const double *U = gauge + ((size_t)src * 4 + mu) * 18;
+  S *o = out + (size_t)i * 18;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      double re, im;
+      if (!bw) { re = U[(a * 3 + b) * 2]; im = U[(a * 3 + b) * 2 + 1]; }
+      else { re = U[(b * 3 + a) * 2]; im = -U[(b * 3 + a) * 2 + 1]; }
+      re *= sign;
+      im *= sign;
+      if constexpr (std::is_same<S, bf16>::value) {
+        o[(a * 3 + b) * 2].bits = float_to_bf16((float)re);
+        o[(a * 3 + b) * 2 + 1].bits = float_to_bf16((float)im);
+      } else {
+        o[(a * 3 + b) * 2] = (S)re;
+        o[(a * 3 + b) * 2 + 1] = (S)im;
+      }
+    }
+}
+
+hipError_t pack_links(int prec, void *out, const double *gauge, const int *lex_of_cb, const int *nbr_lex, int parity,
+                      int Vh, int Lt, int Lxyz, double tbc, hipStream_t st) {
+  (void)parity;
+  const int n = Vh * 8, blk = 256;
+  MSPCG_PREC_SWITCH(prec, hipLaunchKernelGGL(k_pack_links<S>, dim3((n + blk - 1) / blk), dim3(blk), 0, st,
+                                             reinterpret_cast<S *>(out), gauge, lex_of_cb, nbr_lex, Vh, Lt, Lxyz, tbc));
+  return hipGetLastError();
+}
+
+}  // namespace mspcg

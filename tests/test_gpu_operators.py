@@ -1,0 +1,158 @@
+"""GPU parity of the operators (through the C ABI) against the FP64 CPU oracle.
+
+Sizes span several workgroup tiles and a ragged last tile; index work is
+compared bit-exactly, floating point within the per-application tolerance
+(FP64 1e-13, FP32 1e-6, FP16/BF16 with per-site norm 5e-3).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1811_08488_amd import mspcg as M
+from tests import lattice_helpers as H
+from tests.gpu_util import PNAME, PRECS, TOL, Setup, rel, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+LATTICES = [((8, 8, 8, 8), 8), ((6, 4, 2, 10), 12)]
+
+
+@pytest.fixture(scope="module", params=LATTICES, ids=lambda p: "x".join(map(str, p[0])) + f"_ls{p[1]}")
+def S(request):
+    require_gpu()
+    L, Ls = request.param
+    return Setup(L, Ls, "mobius", seed=3)
+
+
+@pytest.fixture(scope="module")
+def S_shamir():
+    require_gpu()
+    return Setup((8, 4, 4, 6), 8, "shamir", seed=4)
+
+
+@pytest.mark.parametrize("parity", [0, 1])
+def test_site_maps_bit_exact(S, parity):
+    lex, nbr = S.h.site_maps(parity)
+    olex, onbr = O.site_maps(S.L, parity)
+    assert np.array_equal(lex, olex)
+    assert np.array_equal(nbr, onbr)
+
+
+@pytest.mark.parametrize("L,nblk,block", [((8, 8, 8, 8), (2, 2, 2, 2), 5), ((10, 8, 6, 12), (3, 2, 1, 2), 7),
+                                          ((10, 8, 6, 12), (3, 2, 1, 2), 0)])
+def test_block_domains_match_brute_force(L, nblk, block):
+    require_gpu()
+    s = Setup(L, 4, "mobius", seed=5)
+    be, o1, e2 = s.h.block_sites(nblk, block)
+    bBe, bO1, bE2 = H.halo_sets_bfs(L, nblk, block)
+    assert sorted(be.tolist()) == bBe and sorted(o1.tolist()) == bO1 and sorted(e2.tolist()) == bE2
+    assert len(set(e2.tolist())) == len(e2) and len(set(o1.tolist())) == len(o1)
+    # B_e is in block-local lexicographic order
+    c = H.coords_of_lex(L)[be]
+    key = [tuple(reversed(((cc - c.min(0)) % np.array(L)).tolist())) for cc in c]
+    assert key == sorted(key)
+    # the oracle's block membership agrees
+    blk = O.block_of_site(L, nblk)
+    assert np.all(blk[be] == block)
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PNAME[p])
+@pytest.mark.parametrize("dagger", [0, 1])
+@pytest.mark.parametrize("out_parity", [0, 1])
+def test_dslash_eo(S, prec, dagger, out_parity):
+    nrhs = 2 if prec == M.F64 else 1
+    x = S.rand(nrhs, 10 + dagger + 2 * out_parity)
+    fin = S.h.upload(x, 1 - out_parity, prec)
+    fout = S.h.field(prec, nrhs, out_parity)
+    S.h.dslash_eo(fout, fin, dagger)
+    got = S.h.download(fout)
+    for r in range(nrhs):
+        want = O.dslash_eo(S.oa, S.U, x[r], out_parity, dagger)
+        assert rel(got[r], want) <= TOL[prec], (PNAME[prec], r, rel(got[r], want))
+
+
+def test_dslash_eo_shamir(S_shamir):
+    S = S_shamir
+    x = S.rand(1, 20)
+    for dagger in (0, 1):
+        fin = S.h.upload(x, 1)
+        fout = S.h.field(M.F64, 1, 0)
+        S.h.dslash_eo(fout, fin, dagger)
+        assert rel(S.h.download(fout)[0], O.dslash_eo(S.oa, S.U, x[0], 0, dagger)) <= 1e-13
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PNAME[p])
+@pytest.mark.parametrize("dagger", [0, 1])
+def test_m5inv(S, prec, dagger):
+    x = S.rand(1, 30 + dagger)
+    fin = S.h.upload(x, 0, prec)
+    fout = S.h.field(prec, 1, 0)
+    S.h.m5inv(fout, fin, dagger)
+    want = O.op5(S.oa, x[0], O.M5INV_DAG if dagger else O.M5INV, 0)
+    assert rel(S.h.download(fout)[0], want) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PNAME[p])
+def test_mdagm(S, prec):
+    nrhs = 2 if prec == M.F64 else 1
+    x = S.rand(nrhs, 40)
+    fin = S.h.upload(x, 0, prec)
+    fout = S.h.field(prec, nrhs, 0)
+    S.h.mdagm(fout, fin)
+    got = S.h.download(fout)
+    for r in range(nrhs):
+        want = O.mdagm(S.oa, S.U, x[r])
+        assert rel(got[r], want) <= TOL[prec], (PNAME[prec], rel(got[r], want))
+
+
+def test_mdagm_shamir(S_shamir):
+    S = S_shamir
+    x = S.rand(1, 41)
+    fout = S.h.field(M.F64, 1, 0)
+    S.h.mdagm(fout, S.h.upload(x, 0))
+    assert rel(S.h.download(fout)[0], O.mdagm(S.oa, S.U, x[0])) <= 1e-13
+
+
+def _oracle_block_sum(S, x, nblk):
+    nb = int(np.prod(nblk))
+    return sum(O.block_op(S.oa, S.U, x, nblk, b) for b in range(nb))
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PNAME[p])
+@pytest.mark.parametrize("L,Ls,nblk", [((8, 8, 8, 8), 8, (2, 2, 2, 2)), ((10, 8, 6, 12), 4, (3, 2, 1, 2))])
+def test_block_apply(L, Ls, nblk, prec):
+    require_gpu()
+    S = Setup(L, Ls, "mobius", seed=6)
+    x = S.rand(1, 50)
+    fout = S.h.field(M.F64, 1, 0)
+    S.h.block_apply(fout, S.h.upload(x, 0), nblk, prec)
+    want = _oracle_block_sum(S, x[0], nblk)
+    assert rel(S.h.download(fout)[0], want) <= TOL[prec], (PNAME[prec], rel(S.h.download(fout)[0], want))
+
+
+def test_prepare_and_reconstruct(S):
+    rng = np.random.default_rng(7)
+    V = int(np.prod(S.L))
+    phi = H.rand_c(rng, (V, S.Ls, 4, 3))
+    b_o, _ = O.prepare_rhs(S.oa, S.U, phi)
+    phi_e, phi_o = H.full_to_cb(S.L, phi, 0), H.full_to_cb(S.L, phi, 1)
+    fb = S.h.field(M.F64, 1, 0)
+    fe, fo = S.h.upload(phi_e, 0), S.h.upload(phi_o, 1)
+    S.h.prepare_rhs(fb, fe, fo)
+    assert rel(S.h.download(fb)[0], b_o) <= 1e-13
+    psi_e = H.rand_c(rng, (V // 2, S.Ls, 4, 3))
+    full = O.reconstruct(S.oa, S.U, psi_e, phi)
+    fpo = S.h.field(M.F64, 1, 1)
+    S.h.reconstruct(fpo, S.h.upload(psi_e, 0), fo)
+    assert rel(S.h.download(fpo)[0], H.full_to_cb(S.L, full, 1)) <= 1e-13
+
+
+def test_conversions_round_trip(S):
+    x = S.rand(1, 60)
+    for prec, tol in ((M.F32, 1e-7), (M.F16, 1e-3), (M.BF16, 8e-3)):
+        back = S.h.download(S.h.upload(x, 0, prec))
+        assert rel(back, x) <= tol
+    # an all-zero site survives the per-site norm
+    x[0, 3] = 0
+    back = S.h.download(S.h.upload(x, 0, M.F16))
+    assert np.all(back[0, 3] == 0) and np.isfinite(back).all()
