@@ -23,10 +23,16 @@
  * Memory
  * ------
  * Gauge: device FP64, [lex][mu][row][col][re,im] (V*4*18 doubles).
- * Fields (mspcg_field): device memory owned by the caller, one parity,
- *   layout [rhs][cb][s][spin][colour][re,im] (24 reals per 5D site) in the
- *   storage type `prec`.  For MSPCG_F16 / MSPCG_BF16 the stored values are
- *   v / n with one FP32 scale n per 5D site in `norm`, laid out [rhs][cb][s]
+ * Fields (mspcg_field): device memory owned by the caller, one parity, in the
+ *   storage type `prec`.  A 5D site holds 24 reals, index
+ *   k = (spin*3 + colour)*2 + re/im.  They are cut into 16-byte chunks of
+ *   C = 2 (F64), 4 (F32) or 8 (F16, BF16) reals, and the fifth dimension is
+ *   interleaved inside each chunk position:
+ *     real k of site (rhs, cb, s) is element ((((rhs*V/2 + cb)*(24/C) + k/C)*Ls + s)*C + k%C
+ *   i.e. [rhs][cb][chunk][s][C]: the Ls spinors of one 4D site are one
+ *   contiguous block, and lanes holding consecutive s load consecutive 16-byte
+ *   words.  For MSPCG_F16 / MSPCG_BF16 the stored values are v / n with one
+ *   FP32 scale n per 5D site in `norm`, laid out [rhs][cb][s]
  *   (n = max |v_i| over the 24 reals; n = 0 means an all-zero site).
  * The library never frees caller memory and keeps no caller pointer after a
  * call returns.  The handle owns its gauge copies, index tables, workspaces

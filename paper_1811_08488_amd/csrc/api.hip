@@ -3,6 +3,7 @@
 // without the multisplitting preconditioner).
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -121,6 +122,9 @@ struct mspcg_handle {
   OwnedVec tmp_o, tmp_e, tmp_o2, tmp_e2, sr, sp, sq, sz;
   DBuf partial, scal;
   std::map<std::vector<int>, std::unique_ptr<BlockGeom>> blocks;
+  // sites per workgroup chosen by the autotuner, per kernel variant and shape
+  std::map<std::vector<int>, int> tuned;
+  bool autotune = true;
 };
 
 namespace {
@@ -253,10 +257,60 @@ HopArgs base_args(mspcg_handle *h, int nrhs) {
   return a;
 }
 
+// Launch a hop with the tuned number of sites per workgroup; returns the grid
+// size (= number of partial sums written when `dot`).  The first launch of a
+// variant/shape times every candidate with HIP events on the stream (the
+// kernels are pure functions of their inputs, so repeating them is harmless)
+// and keeps the fastest; the default shape wins ties within 3%.
+int run_hop(mspcg_handle *h, int list_kind, int prec, int dag, int pre, int epi, int dot, HopArgs a,
+            hipStream_t st) {
+  const std::vector<int> key = {list_kind, prec, dag, pre, epi, dot, a.Ls, a.nrhs, a.nsites};
+  auto it = h->tuned.find(key);
+  int n = 0;
+  if (it != h->tuned.end()) {
+    n = it->second;
+  } else {
+    const int n0 = pick_nsite(a.nrhs, a.Ls);
+    n = n0;
+    if (h->autotune) {
+      hipEvent_t e0, e1;
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      float best = 0;
+      for (int c = 1; c <= kPad; c *= 2) {
+        const int thr = c * a.nrhs * a.Ls;
+        if (thr > 256 || (thr < 64 && 2 * thr <= 256 && c < kPad)) continue;
+        a.nsite_wg = c;
+        if (launch_hop(prec, dag, pre, epi, dot, a, st) != hipSuccess) {
+          (void)hipGetLastError();
+          continue;
+        }
+        HIPCHK(hipEventRecord(e0, st));
+        for (int rep = 0; rep < 3; ++rep) HIPCHK(launch_hop(prec, dag, pre, epi, dot, a, st));
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (c == n0) ms *= 0.97f;
+        if (best == 0 || ms < best) {
+          best = ms;
+          n = c;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+    }
+    h->tuned[key] = n;
+  }
+  a.nsite_wg = n;
+  HIPCHK(launch_hop(prec, dag, pre, epi, dot, a, st));
+  return (a.nsites + n - 1) / n;
+}
+
 // Full-lattice hop: output parity p (site list = all cb), input parity 1-p.
-void global_hop(mspcg_handle *h, int prec, int nrhs, int p, const Vec &out, const Vec &in, int dag, int pre, int epi,
-                double scale, const double *mat, const Vec *other, double *partial, const Vec *dotw,
-                hipStream_t st) {
+int global_hop(mspcg_handle *h, int prec, int nrhs, int p, const Vec &out, const Vec &in, int dag, int pre, int epi,
+               double scale, const double *mat, const Vec *other, double *partial, const Vec *dotw,
+               hipStream_t st) {
   ensure_links(h, prec, st);
   HopArgs a = base_args(h, nrhs);
   a.nsites = h->Vh;
@@ -282,18 +336,13 @@ void global_hop(mspcg_handle *h, int prec, int nrhs, int p, const Vec &out, cons
     a.dotw_norm = dotw->norm;
     a.dotw_stride = h->Vh;
   }
-  HIPCHK(launch_hop(prec, dag, pre, epi, partial ? 1 : 0, a, st));
-}
-
-int hop_grid(mspcg_handle *h, int nsites, int nrhs) {
-  const int n = pick_nsite(nrhs, h->par.Ls);
-  return (nsites + n - 1) / n;
+  return run_hop(h, 0, prec, dag, pre, epi, partial ? 1 : 0, a, st);
 }
 
 // out_e = D_PC^+ D_PC in_e (all four hops fused with their fifth-dimension
 // neighbours); optional partial Re<in, out> per workgroup.
-void apply_mdagm(mspcg_handle *h, int prec, int nrhs, const Vec &out, const Vec &in, const Vec &to, const Vec &te,
-                 double *partial, hipStream_t st) {
+int apply_mdagm(mspcg_handle *h, int prec, int nrhs, const Vec &out, const Vec &in, const Vec &to, const Vec &te,
+                double *partial, hipStream_t st) {
   // c_o = M_phi M_5^{-1} (-1/2 H_oe M_phi in)
   global_hop(h, prec, nrhs, 1, to, in, 0, 1, EPI_DENSE, -0.5, h->d_x1.as<double>(), nullptr, nullptr, nullptr, st);
   // y_e = M_5 in + 1/2 H_eo c_o  (= D_PC in)
@@ -301,7 +350,7 @@ void apply_mdagm(mspcg_handle *h, int prec, int nrhs, const Vec &out, const Vec 
   // f_o = M_5^{-+} M_phi^+ (-1/2 H^+_oe y_e)
   global_hop(h, prec, nrhs, 1, to, te, 1, 0, EPI_DENSE, -0.5, h->d_x3.as<double>(), nullptr, nullptr, nullptr, st);
   // out = M_5^+ y + 1/2 M_phi^+ H^+_eo f  (= D_PC^+ y)
-  global_hop(h, prec, nrhs, 0, out, to, 1, 0, EPI_M5DAG_MPHIDAG, 0.5, nullptr, &te, partial, &in, st);
+  return global_hop(h, prec, nrhs, 0, out, to, 1, 0, EPI_M5DAG_MPHIDAG, 0.5, nullptr, &te, partial, &in, st);
 }
 
 void ensure_fp64_temps(mspcg_handle *h, int nrhs) {
@@ -505,13 +554,13 @@ HopArgs block_hop_args(mspcg_handle *h, int nrhs, int nsites, const int *site_cb
 
 // out = A_s in for every block at once on the halo-extended domains
 // (B_e -> O1 -> E2 -> O1 -> B_e); optional partial Re<in, out> per workgroup.
-void block_hops(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, const Vec &in, const Vec &out, double *partial,
-                hipStream_t st) {
+int block_hops(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, const Vec &in, const Vec &out, double *partial,
+               hipStream_t st) {
   HopArgs a1 = block_hop_args(h, nrhs, bg->o1_tot, bg->d_o1_cb.as<int>(), bg->d_o1_nbr_be.as<int>(), in,
                               bg->o1v.v, 1, prec);
   a1.scale = -0.5;
   a1.mat = h->d_x1.as<double>();
-  HIPCHK(launch_hop(prec, 0, 1, EPI_DENSE, 0, a1, st));
+  run_hop(h, 1, prec, 0, 1, EPI_DENSE, 0, a1, st);
   HopArgs a2 = block_hop_args(h, nrhs, bg->e2_tot, bg->d_e2_cb.as<int>(), bg->d_e2_nbr.as<int>(), bg->o1v.v,
                               bg->e2v.v, 0, prec);
   a2.scale = 0.5;
@@ -519,12 +568,12 @@ void block_hops(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, const Vec &i
   a2.other_norm = in.norm;
   a2.other_stride = in.stride;
   a2.other_idx = bg->d_e2_be.as<int>();
-  HIPCHK(launch_hop(prec, 0, 0, EPI_M5_OTHER, 0, a2, st));
+  run_hop(h, 2, prec, 0, 0, EPI_M5_OTHER, 0, a2, st);
   HopArgs a3 = block_hop_args(h, nrhs, bg->o1_tot, bg->d_o1_cb.as<int>(), bg->d_o1_nbr_e2.as<int>(), bg->e2v.v,
                               bg->o1v.v, 1, prec);
   a3.scale = -0.5;
   a3.mat = h->d_x3.as<double>();
-  HIPCHK(launch_hop(prec, 1, 0, EPI_DENSE, 0, a3, st));
+  run_hop(h, 3, prec, 1, 0, EPI_DENSE, 0, a3, st);
   HopArgs a4 = block_hop_args(h, nrhs, bg->be_tot, bg->d_be_cb.as<int>(), bg->d_be_nbr.as<int>(), bg->o1v.v, out,
                               0, prec);
   a4.scale = 0.5;
@@ -538,7 +587,8 @@ void block_hops(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, const Vec &i
     a4.dotw_norm = in.norm;
     a4.dotw_stride = in.stride;
   }
-  HIPCHK(launch_hop(prec, 1, 0, EPI_M5DAG_MPHIDAG, partial ? 1 : 0, a4, st));
+  const int grid = run_hop(h, 4, prec, 1, 0, EPI_M5DAG_MPHIDAG, partial ? 1 : 0, a4, st);
+  return (bg->be_tot + grid - 1) / grid;  // sites per workgroup of the last hop
 }
 
 BlockArgs block_args(mspcg_handle *h, BlockGeom *bg, int nrhs) {
@@ -569,8 +619,9 @@ void run_block_cg(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int k, con
   HIPCHK(block_gather(prec, ba, bg->x.v, bg->r.v, bg->p.v, r, rr, n_total, part, st));
   HIPCHK(block_scalars(2, ba, part, scal, st));
   for (int it = 0; it < k; ++it) {
-    block_hops(h, bg, prec, nrhs, bg->p.v, bg->Ap.v, part, st);
-    HIPCHK(block_scalars(0, ba, part, scal, st));
+    BlockArgs ba4 = ba;
+    ba4.nsite_wg = block_hops(h, bg, prec, nrhs, bg->p.v, bg->Ap.v, part, st);
+    HIPCHK(block_scalars(0, ba4, part, scal, st));
     HIPCHK(block_update_xr(prec, ba, bg->x.v, bg->r.v, bg->p.v, bg->Ap.v, scal, part, st));
     if (it + 1 < k) {
       HIPCHK(block_scalars(1, ba, part, scal, st));
@@ -612,8 +663,7 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
     h->sp.ensure(MSPCG_F64, nrhs, h->Vh, Ls);
     h->sq.ensure(MSPCG_F64, nrhs, h->Vh, Ls);
     if (pc) h->sz.ensure(MSPCG_F64, nrhs, h->Vh, Ls);
-    const int hop_parts = hop_grid(h, h->Vh, nrhs);
-    const size_t nparts_max = std::max<size_t>((size_t)std::max(hop_parts, kBlasGrid), bg ? (size_t)bg->be_tot : 0);
+    const size_t nparts_max = std::max<size_t>((size_t)std::max(h->Vh, kBlasGrid), bg ? (size_t)bg->be_tot : 0);
     h->partial.ensure(nparts_max * nrhs * sizeof(double));
     h->scal.ensure((size_t)nrhs * 8 * sizeof(double) + 64);
     double *part = h->partial.as<double>();
@@ -682,7 +732,7 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
       HIPCHK(blas_axpby(pd, 1.0, zd, 0.0, zd, n, nrhs, st));  // p = z
       HIPCHK(hipMemcpyAsync(w.rho, w.tmp, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
       while (it < s->max_iter) {
-        apply_mdagm(h, MSPCG_F64, nrhs, Q, P, h->tmp_o.v, h->tmp_e.v, part, st);
+        const int hop_parts = apply_mdagm(h, MSPCG_F64, nrhs, Q, P, h->tmp_o.v, h->tmp_e.v, part, st);
         HIPCHK(blas_reduce(part, hop_parts, nrhs, w.pap, st));
         HIPCHK(solver_scalars(0, nrhs, w.active, w.rho, w.pap, w.alpha, st));
         HIPCHK(blas_update_xr(xd, rd, pd, qd, w.alpha, n, nrhs, part, st));
@@ -759,6 +809,7 @@ mspcg_status mspcg_create(mspcg_handle **hp, const mspcg_dwf *p, const double *g
     h->Vh = (int)(V / 2);
     h->Lxyz = p->L[0] * p->L[1] * p->L[2];
     h->stream = S(stream);
+    if (const char *e = std::getenv("MSPCG_AUTOTUNE")) h->autotune = std::atoi(e) != 0;
     h->alpha5 = p->b * (4.0 - p->M5) + 1.0;
     h->beta5 = 1.0 - p->c * (4.0 - p->M5);
     const int Ls = p->Ls;
@@ -1040,7 +1091,7 @@ mspcg_status mspcg_block_apply(mspcg_handle *h, mspcg_field *out, const mspcg_fi
     const double n_total = (double)h->Vh * h->par.Ls * 24;
     double *part = bg->partial.as<double>();
     HIPCHK(block_gather(prec, ba, bg->x.v, bg->r.v, bg->p.v, vec_of(h, in), nullptr, n_total, part, st));
-    block_hops(h, bg, prec, nrhs, bg->p.v, bg->Ap.v, nullptr, st);
+    (void)block_hops(h, bg, prec, nrhs, bg->p.v, bg->Ap.v, nullptr, st);
     HIPCHK(block_scatter(prec, ba, vec_of(h, out), bg->Ap.v, Vec(), nullptr, n_total, part, st));
   });
 }
@@ -1051,7 +1102,7 @@ mspcg_status mspcg_convert(mspcg_handle *h, mspcg_field *out, const mspcg_field 
     check_field(h, out, "out");
     check_field(h, in, "in");
     if (out->nrhs != in->nrhs || out->parity != in->parity) fail(MSPCG_EINVAL, "convert: nrhs/parity mismatch");
-    HIPCHK(launch_convert(vec_of(h, out), vec_of(h, in), in->nrhs, (long long)h->Vh * h->par.Ls, S(stream)));
+    HIPCHK(launch_convert(vec_of(h, out), vec_of(h, in), in->nrhs, (long long)h->Vh * h->par.Ls, h->par.Ls, S(stream)));
   });
 }
 

@@ -47,23 +47,35 @@ __device__ __host__ inline uint16_t float_to_bf16(float f) {
 }
 
 // ---------------------------------------------------------------- site load/store
-// A 5D site holds 24 reals [spin][colour][re,im]; `site` counts 5D sites.
+// Field layout: the 24 reals of a 5D site are cut into 16-byte chunks (2
+// doubles, 4 floats or 8 halves) and the fifth dimension is interleaved
+// inside each chunk position:  [rhs][cb][chunk][s][16 bytes].  Lanes that hold
+// consecutive s of one 4D site therefore read consecutive 16-byte words with
+// every load instruction.  `site4` = rhs * stride + cb counts 4D sites of one
+// right-hand side; the per-5D-site norm of F16/BF16 is at site4 * Ls + s.
+template <typename S> struct Chunk {
+  static constexpr int kReals = 16 / sizeof(S);  // reals per chunk
+  static constexpr int kCount = 24 / kReals;     // chunks per 5D site
+};
+template <typename S>
+__device__ __host__ inline size_t chunk_index(size_t site4, int s, int Ls, int c) {
+  return ((site4 * Chunk<S>::kCount + c) * (size_t)Ls + s) * Chunk<S>::kReals;
+}
+
 template <typename R>
-__device__ inline void load24(const double *base, const float *, size_t site, R v[24]) {
-  const double2 *p = reinterpret_cast<const double2 *>(base + site * 24);
+__device__ inline void load24(const double *base, const float *, size_t site4, int s, int Ls, R v[24]) {
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
-    double2 t = p[k];
+    const double2 t = *reinterpret_cast<const double2 *>(base + chunk_index<double>(site4, s, Ls, k));
     v[2 * k] = (R)t.x;
     v[2 * k + 1] = (R)t.y;
   }
 }
 template <typename R>
-__device__ inline void load24(const float *base, const float *, size_t site, R v[24]) {
-  const float4 *p = reinterpret_cast<const float4 *>(base + site * 24);
+__device__ inline void load24(const float *base, const float *, size_t site4, int s, int Ls, R v[24]) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    float4 t = p[k];
+    const float4 t = *reinterpret_cast<const float4 *>(base + chunk_index<float>(site4, s, Ls, k));
     v[4 * k] = (R)t.x;
     v[4 * k + 1] = (R)t.y;
     v[4 * k + 2] = (R)t.z;
@@ -71,13 +83,12 @@ __device__ inline void load24(const float *base, const float *, size_t site, R v
   }
 }
 template <typename R>
-__device__ inline void load24(const _Float16 *base, const float *norm, size_t site, R v[24]) {
-  const uint4 *p = reinterpret_cast<const uint4 *>(base + site * 24);
-  const float n = norm[site];
+__device__ inline void load24(const _Float16 *base, const float *norm, size_t site4, int s, int Ls, R v[24]) {
+  const float n = norm[site4 * Ls + s];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    uint4 t = p[k];
-    uint32_t w[4] = {t.x, t.y, t.z, t.w};
+    const uint4 t = *reinterpret_cast<const uint4 *>(base + chunk_index<_Float16>(site4, s, Ls, k));
+    const uint32_t w[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       union { uint32_t u; _Float16 h[2]; } c;
@@ -88,13 +99,12 @@ __device__ inline void load24(const _Float16 *base, const float *norm, size_t si
   }
 }
 template <typename R>
-__device__ inline void load24(const bf16 *base, const float *norm, size_t site, R v[24]) {
-  const uint4 *p = reinterpret_cast<const uint4 *>(base + site * 24);
-  const float n = norm[site];
+__device__ inline void load24(const bf16 *base, const float *norm, size_t site4, int s, int Ls, R v[24]) {
+  const float n = norm[site4 * Ls + s];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    uint4 t = p[k];
-    uint32_t w[4] = {t.x, t.y, t.z, t.w};
+    const uint4 t = *reinterpret_cast<const uint4 *>(base + chunk_index<bf16>(site4, s, Ls, k));
+    const uint32_t w[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       v[8 * k + 2 * j] = (R)(bf16_to_float((uint16_t)(w[j] & 0xffffu)) * n);
@@ -104,17 +114,18 @@ __device__ inline void load24(const bf16 *base, const float *norm, size_t site, 
 }
 
 template <typename R>
-__device__ inline void store24(double *base, float *, size_t site, const R v[24]) {
-  double2 *p = reinterpret_cast<double2 *>(base + site * 24);
+__device__ inline void store24(double *base, float *, size_t site4, int s, int Ls, const R v[24]) {
 #pragma unroll
-  for (int k = 0; k < 12; ++k) p[k] = make_double2((double)v[2 * k], (double)v[2 * k + 1]);
+  for (int k = 0; k < 12; ++k)
+    *reinterpret_cast<double2 *>(base + chunk_index<double>(site4, s, Ls, k)) =
+        make_double2((double)v[2 * k], (double)v[2 * k + 1]);
 }
 template <typename R>
-__device__ inline void store24(float *base, float *, size_t site, const R v[24]) {
-  float4 *p = reinterpret_cast<float4 *>(base + site * 24);
+__device__ inline void store24(float *base, float *, size_t site4, int s, int Ls, const R v[24]) {
 #pragma unroll
   for (int k = 0; k < 6; ++k)
-    p[k] = make_float4((float)v[4 * k], (float)v[4 * k + 1], (float)v[4 * k + 2], (float)v[4 * k + 3]);
+    *reinterpret_cast<float4 *>(base + chunk_index<float>(site4, s, Ls, k)) =
+        make_float4((float)v[4 * k], (float)v[4 * k + 1], (float)v[4 * k + 2], (float)v[4 * k + 3]);
 }
 template <typename R>
 __device__ inline float site_scale(const R v[24], float &inv) {
@@ -125,10 +136,9 @@ __device__ inline float site_scale(const R v[24], float &inv) {
   return m;
 }
 template <typename R>
-__device__ inline void store24(_Float16 *base, float *norm, size_t site, const R v[24]) {
+__device__ inline void store24(_Float16 *base, float *norm, size_t site4, int s, int Ls, const R v[24]) {
   float inv;
-  norm[site] = site_scale(v, inv);
-  uint4 *p = reinterpret_cast<uint4 *>(base + site * 24);
+  norm[site4 * Ls + s] = site_scale(v, inv);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     uint32_t w[4];
@@ -139,14 +149,13 @@ __device__ inline void store24(_Float16 *base, float *norm, size_t site, const R
       c.h[1] = (_Float16)((float)v[8 * k + 2 * j + 1] * inv);
       w[j] = c.u;
     }
-    p[k] = make_uint4(w[0], w[1], w[2], w[3]);
+    *reinterpret_cast<uint4 *>(base + chunk_index<_Float16>(site4, s, Ls, k)) = make_uint4(w[0], w[1], w[2], w[3]);
   }
 }
 template <typename R>
-__device__ inline void store24(bf16 *base, float *norm, size_t site, const R v[24]) {
+__device__ inline void store24(bf16 *base, float *norm, size_t site4, int s, int Ls, const R v[24]) {
   float inv;
-  norm[site] = site_scale(v, inv);
-  uint4 *p = reinterpret_cast<uint4 *>(base + site * 24);
+  norm[site4 * Ls + s] = site_scale(v, inv);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     uint32_t w[4];
@@ -154,7 +163,7 @@ __device__ inline void store24(bf16 *base, float *norm, size_t site, const R v[2
     for (int j = 0; j < 4; ++j)
       w[j] = (uint32_t)float_to_bf16((float)v[8 * k + 2 * j] * inv) |
              ((uint32_t)float_to_bf16((float)v[8 * k + 2 * j + 1] * inv) << 16);
-    p[k] = make_uint4(w[0], w[1], w[2], w[3]);
+    *reinterpret_cast<uint4 *>(base + chunk_index<bf16>(site4, s, Ls, k)) = make_uint4(w[0], w[1], w[2], w[3]);
   }
 }
 

@@ -18,7 +18,7 @@ enum Epi {
   EPI_M5DAG_MPHIDAG = 4,  // out = M_5^+ other + scale * M_phi^+ hop
 };
 
-// A field stored as [rhs][site][s][24] over a list of `stride` sites.
+// A field [rhs][site][chunk][s][16 bytes] over a list of `stride` sites.
 struct Vec {
   void *data = nullptr;
   float *norm = nullptr;  // F16/BF16 only: [rhs][site][s]
@@ -70,7 +70,7 @@ struct Op5Args {
 hipError_t launch_op5(int prec, const Op5Args &a, hipStream_t st);
 
 // Precision conversion of [rhs][site][s][24] fields.
-hipError_t launch_convert(const Vec &out, const Vec &in, int nrhs, long long nsites5, hipStream_t st);
+hipError_t launch_convert(const Vec &out, const Vec &in, int nrhs, long long nsites5, int Ls, hipStream_t st);
 
 // ------------------------------------------------------------- FP64 BLAS (outer solver)
 // n = reals per right-hand side; vectors are [nrhs][n] doubles.

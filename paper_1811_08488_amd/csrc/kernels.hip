@@ -68,10 +68,19 @@ __device__ inline void dense_chiral(R *lds, const R *matT, int nthr, int tid, in
   for (int k = 0; k < 24; ++k) v[k] = scale * o[k];
 }
 
-// Workgroup sum of `val` per right-hand side into partial[blockIdx.x * nrhs + r]
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
+// with its own L2.  Renumbering them so that every XCD works on one
+// contiguous range of tiles keeps the neighbours a tile gathers (x, y and z
+// hops land a few tiles away) in the same L2.  Bijective on [0, n).
+__device__ inline int xcd_tile(int b, int n) {
+  const int q = n >> 3, rem = n & 7, x = b & 7, k = b >> 3;
+  return x * q + min(x, rem) + k;
+}
+
+// Workgroup sum of `val` per right-hand side into partial[tile * nrhs + r]
 // (fixed order: deterministic).  Uses the LDS region as doubles.
 __device__ inline void wg_partial(double *ldsd, int nthr, int tid, int Ls, int nrhs, int nsite_wg, double val,
-                                  double *partial) {
+                                  double *partial, int tile) {
   __syncthreads();
   ldsd[tid] = val;
   __syncthreads();
@@ -85,7 +94,7 @@ __device__ inline void wg_partial(double *ldsd, int nthr, int tid, int Ls, int n
   if (tid < nrhs) {
     double acc = 0;
     for (int g = 0; g < nsite_wg; ++g) acc += ldsd[nthr + g * nrhs + tid];
-    partial[(size_t)blockIdx.x * nrhs + tid] = acc;
+    partial[(size_t)tile * nrhs + tid] = acc;
   }
 }
 
@@ -107,7 +116,8 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
   const int rem = tid - sl * G;
   const int r = rem / Ls;
   const int s = rem - r * Ls;
-  const int site = blockIdx.x * a.nsite_wg + sl;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int site = tile * a.nsite_wg + sl;
   const int cb = (site < a.nsites) ? a.site_cb[site] : -1;
   const bool active = cb >= 0;
 
@@ -128,7 +138,7 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     const int j = active ? a.nbr[(size_t)site * 8 + d] : -1;
     R v[24];
     if (j >= 0)
-      load24<R>(in, a.in_norm, ((size_t)r * a.in_stride + j) * Ls + s, v);
+      load24<R>(in, a.in_norm, (size_t)r * a.in_stride + j, s, Ls, v);
     else
       zero24(v);
     if (PRE) pchi_comb<R>(lds, nthr, tid, s, Ls, (R)a.mphi_b, (R)a.mphi_c, (R)a.mf, 0, v);
@@ -173,7 +183,7 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     const int oi = active ? (a.other_idx ? a.other_idx[site] : site) : -1;
     R o[24];
     if (oi >= 0)
-      load24<R>(reinterpret_cast<const S *>(a.other), a.other_norm, ((size_t)r * a.other_stride + oi) * Ls + s, o);
+      load24<R>(reinterpret_cast<const S *>(a.other), a.other_norm, (size_t)r * a.other_stride + oi, s, Ls, o);
     else
       zero24(o);
     // M_5 = alpha - beta P_chi ; M_5^+ = alpha - beta P_chi^+
@@ -182,19 +192,19 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     for (int k = 0; k < 24; ++k) acc[k] += o[k];
   }
 
-  if (active) store24<R>(reinterpret_cast<S *>(a.out), a.out_norm, ((size_t)r * a.out_stride + site) * Ls + s, acc);
+  if (active) store24<R>(reinterpret_cast<S *>(a.out), a.out_norm, (size_t)r * a.out_stride + site, s, Ls, acc);
 
   if (DOT) {
     double val = 0;
     if (active) {
       R w[24];
-      load24<R>(reinterpret_cast<const S *>(a.dotw), a.dotw_norm, ((size_t)r * a.dotw_stride + site) * Ls + s, w);
+      load24<R>(reinterpret_cast<const S *>(a.dotw), a.dotw_norm, (size_t)r * a.dotw_stride + site, s, Ls, w);
       R t = 0;
 #pragma unroll
       for (int k = 0; k < 24; ++k) t += w[k] * acc[k];
       val = (double)t;
     }
-    wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, a.nrhs, a.nsite_wg, val, a.partial);
+    wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, a.nrhs, a.nsite_wg, val, a.partial, tile);
   }
 }
 
@@ -262,16 +272,16 @@ __global__ void __launch_bounds__(256) op5_kernel(const Op5Args a) {
       matT[i] = (R)a.mat[chi * Ls * Ls + so * Ls + t];
     }
   R v[24];
-  const size_t idx = ((size_t)r * a.stride + site) * Ls + s;
+  const size_t idx = (size_t)r * a.stride + site;
   if (active)
-    load24<R>(reinterpret_cast<const S *>(a.in), a.in_norm, idx, v);
+    load24<R>(reinterpret_cast<const S *>(a.in), a.in_norm, idx, s, Ls, v);
   else
     zero24(v);
   if (a.dense)
     dense_chiral<R>(lds, matT, nthr, tid, s, Ls, R(1), v);
   else
     pchi_comb<R>(lds, nthr, tid, s, Ls, (R)a.a, (R)a.b, (R)a.mf, a.dag, v);
-  if (active) store24<R>(reinterpret_cast<S *>(a.out), a.out_norm, idx, v);
+  if (active) store24<R>(reinterpret_cast<S *>(a.out), a.out_norm, idx, s, Ls, v);
 }
 
 hipError_t launch_op5(int prec, const Op5Args &a, hipStream_t st) {
@@ -292,55 +302,45 @@ hipError_t launch_op5(int prec, const Op5Args &a, hipStream_t st) {
 
 // ---------------------------------------------------------------- conversion
 template <typename SO, typename SI>
-__global__ void convert_kernel(SO *out, float *out_norm, const SI *in, const float *in_norm, long long n5) {
+__global__ void convert_kernel(SO *out, float *out_norm, const SI *in, const float *in_norm, long long n5, int Ls) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n5) return;
-  float v[24];
-  if (sizeof(SI) == 8) {
+  const size_t site4 = (size_t)(i / Ls);
+  const int s = (int)(i % Ls);
+  if (sizeof(SI) == 8 || sizeof(SO) == 8) {
     double t[24];
-    load24<double>(reinterpret_cast<const double *>(in), in_norm, i, t);
-    if (sizeof(SO) == 8) {
-      store24<double>(reinterpret_cast<double *>(out), out_norm, i, t);
-      return;
-    }
-#pragma unroll
-    for (int k = 0; k < 24; ++k) v[k] = (float)t[k];
+    load24<double>(in, in_norm, site4, s, Ls, t);
+    store24<double>(out, out_norm, site4, s, Ls, t);
   } else {
-    load24<float>(in, in_norm, i, v);
-  }
-  if (sizeof(SO) == 8) {
-    double t[24];
-#pragma unroll
-    for (int k = 0; k < 24; ++k) t[k] = v[k];
-    store24<double>(reinterpret_cast<double *>(out), out_norm, i, t);
-  } else {
-    store24<float>(out, out_norm, i, v);
+    float v[24];
+    load24<float>(in, in_norm, site4, s, Ls, v);
+    store24<float>(out, out_norm, site4, s, Ls, v);
   }
 }
 
 template <typename SO>
-static hipError_t convert_from(const Vec &out, const Vec &in, long long n5, hipStream_t st) {
+static hipError_t convert_from(const Vec &out, const Vec &in, long long n5, int Ls, hipStream_t st) {
   const int blk = 256;
   const long long grid = (n5 + blk - 1) / blk;
   SO *o = reinterpret_cast<SO *>(out.data);
   switch (in.prec) {
-    case MSPCG_F64: hipLaunchKernelGGL((convert_kernel<SO, double>), dim3(grid), dim3(blk), 0, st, o, out.norm, (const double *)in.data, in.norm, n5); break;
-    case MSPCG_F32: hipLaunchKernelGGL((convert_kernel<SO, float>), dim3(grid), dim3(blk), 0, st, o, out.norm, (const float *)in.data, in.norm, n5); break;
-    case MSPCG_F16: hipLaunchKernelGGL((convert_kernel<SO, _Float16>), dim3(grid), dim3(blk), 0, st, o, out.norm, (const _Float16 *)in.data, in.norm, n5); break;
-    case MSPCG_BF16: hipLaunchKernelGGL((convert_kernel<SO, bf16>), dim3(grid), dim3(blk), 0, st, o, out.norm, (const bf16 *)in.data, in.norm, n5); break;
+    case MSPCG_F64: hipLaunchKernelGGL((convert_kernel<SO, double>), dim3(grid), dim3(blk), 0, st, o, out.norm, (const double *)in.data, in.norm, n5, Ls); break;
+    case MSPCG_F32: hipLaunchKernelGGL((convert_kernel<SO, float>), dim3(grid), dim3(blk), 0, st, o, out.norm, (const float *)in.data, in.norm, n5, Ls); break;
+    case MSPCG_F16: hipLaunchKernelGGL((convert_kernel<SO, _Float16>), dim3(grid), dim3(blk), 0, st, o, out.norm, (const _Float16 *)in.data, in.norm, n5, Ls); break;
+    case MSPCG_BF16: hipLaunchKernelGGL((convert_kernel<SO, bf16>), dim3(grid), dim3(blk), 0, st, o, out.norm, (const bf16 *)in.data, in.norm, n5, Ls); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_convert(const Vec &out, const Vec &in, int nrhs, long long nsites5, hipStream_t st) {
+hipError_t launch_convert(const Vec &out, const Vec &in, int nrhs, long long nsites5, int Ls, hipStream_t st) {
   const long long n5 = nsites5 * nrhs;
   if (n5 <= 0) return hipSuccess;
   switch (out.prec) {
-    case MSPCG_F64: return convert_from<double>(out, in, n5, st);
-    case MSPCG_F32: return convert_from<float>(out, in, n5, st);
-    case MSPCG_F16: return convert_from<_Float16>(out, in, n5, st);
-    case MSPCG_BF16: return convert_from<bf16>(out, in, n5, st);
+    case MSPCG_F64: return convert_from<double>(out, in, n5, Ls, st);
+    case MSPCG_F32: return convert_from<float>(out, in, n5, Ls, st);
+    case MSPCG_F16: return convert_from<_Float16>(out, in, n5, Ls, st);
+    case MSPCG_BF16: return convert_from<bf16>(out, in, n5, Ls, st);
   }
   return hipErrorInvalidValue;
 }
@@ -494,24 +494,24 @@ __global__ void __launch_bounds__(256) k_block_gather(const BlockArgs b, Vec xs,
   if (cb >= 0) {
     const double scale = rr ? (rr[r] > 0 ? sqrt(n_total / rr[r]) : 0.0) : 1.0;
     double t[24];
-    load24<double>(rg, nullptr, ((size_t)r * rg_stride + cb) * Ls + s, t);
+    load24<double>(rg, nullptr, (size_t)r * rg_stride + cb, s, Ls, t);
     R v[24];
 #pragma unroll
     for (int k = 0; k < 24; ++k) v[k] = (R)(scale * t[k]);
-    const size_t o = ((size_t)r * rs.stride + site) * Ls + s;
-    store24<R>(reinterpret_cast<S *>(rs.data), rs.norm, o, v);
+    const size_t o = (size_t)r * rs.stride + site;
+    store24<R>(reinterpret_cast<S *>(rs.data), rs.norm, o, s, Ls, v);
     // read back what was stored so that r and p start identical and the sum matches them
-    load24<R>(reinterpret_cast<const S *>(rs.data), rs.norm, o, v);
-    store24<R>(reinterpret_cast<S *>(ps.data), ps.norm, o, v);
+    load24<R>(reinterpret_cast<const S *>(rs.data), rs.norm, o, s, Ls, v);
+    store24<R>(reinterpret_cast<S *>(ps.data), ps.norm, o, s, Ls, v);
     R z[24];
     zero24(z);
-    store24<R>(reinterpret_cast<S *>(xs.data), xs.norm, o, z);
+    store24<R>(reinterpret_cast<S *>(xs.data), xs.norm, o, s, Ls, z);
     R acc = 0;
 #pragma unroll
     for (int k = 0; k < 24; ++k) acc += v[k] * v[k];
     val = (double)acc;
   }
-  wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, b.nrhs, b.nsite_wg, val, partial);
+  wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, b.nrhs, b.nsite_wg, val, partial, blockIdx.x);
 }
 
 template <typename S>
@@ -528,19 +528,19 @@ __global__ void __launch_bounds__(256) k_block_scatter(const BlockArgs b, double
   if (cb >= 0) {
     const double inv = rr ? (rr[r] > 0 ? sqrt(rr[r] / n_total) : 0.0) : 1.0;
     R v[24];
-    load24<R>(reinterpret_cast<const S *>(xs.data), xs.norm, ((size_t)r * xs.stride + site) * Ls + s, v);
+    load24<R>(reinterpret_cast<const S *>(xs.data), xs.norm, (size_t)r * xs.stride + site, s, Ls, v);
     double z[24], t[24];
 #pragma unroll
     for (int k = 0; k < 24; ++k) z[k] = inv * (double)v[k];
-    const size_t g = ((size_t)r * zg_stride + cb) * Ls + s;
-    store24<double>(zg, nullptr, g, z);
+    const size_t g = (size_t)r * zg_stride + cb;
+    store24<double>(zg, nullptr, g, s, Ls, z);
     if (rg) {
-      load24<double>(rg, nullptr, g, t);
+      load24<double>(rg, nullptr, g, s, Ls, t);
 #pragma unroll
       for (int k = 0; k < 24; ++k) val += z[k] * t[k];
     }
   }
-  wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, b.nrhs, b.nsite_wg, val, partial);
+  wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, b.nrhs, b.nsite_wg, val, partial, blockIdx.x);
 }
 
 template <typename S>
@@ -555,27 +555,27 @@ __global__ void __launch_bounds__(256) k_block_update_xr(const BlockArgs b, Vec 
   double val = 0;
   if (blk >= 0) {
     const R al = (R)scal[((size_t)blk * b.nrhs + r) * kScal + 1];
-    const size_t o = ((size_t)r * xv.stride + site) * Ls + s;
+    const size_t o = (size_t)r * xv.stride + site;
     R x[24], rr[24], p[24], q[24];
-    load24<R>(reinterpret_cast<const S *>(xv.data), xv.norm, o, x);
-    load24<R>(reinterpret_cast<const S *>(rv.data), rv.norm, o, rr);
-    load24<R>(reinterpret_cast<const S *>(pv.data), pv.norm, o, p);
-    load24<R>(reinterpret_cast<const S *>(qv.data), qv.norm, o, q);
+    load24<R>(reinterpret_cast<const S *>(xv.data), xv.norm, o, s, Ls, x);
+    load24<R>(reinterpret_cast<const S *>(rv.data), rv.norm, o, s, Ls, rr);
+    load24<R>(reinterpret_cast<const S *>(pv.data), pv.norm, o, s, Ls, p);
+    load24<R>(reinterpret_cast<const S *>(qv.data), qv.norm, o, s, Ls, q);
 #pragma unroll
     for (int k = 0; k < 24; ++k) {
       x[k] += al * p[k];
       rr[k] -= al * q[k];
     }
-    store24<R>(reinterpret_cast<S *>(xv.data), xv.norm, o, x);
-    store24<R>(reinterpret_cast<S *>(rv.data), rv.norm, o, rr);
+    store24<R>(reinterpret_cast<S *>(xv.data), xv.norm, o, s, Ls, x);
+    store24<R>(reinterpret_cast<S *>(rv.data), rv.norm, o, s, Ls, rr);
     // the norm is taken of the stored (rounded) residual
-    load24<R>(reinterpret_cast<const S *>(rv.data), rv.norm, o, rr);
+    load24<R>(reinterpret_cast<const S *>(rv.data), rv.norm, o, s, Ls, rr);
     R acc = 0;
 #pragma unroll
     for (int k = 0; k < 24; ++k) acc += rr[k] * rr[k];
     val = (double)acc;
   }
-  wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, b.nrhs, b.nsite_wg, val, partial);
+  wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, b.nrhs, b.nsite_wg, val, partial, blockIdx.x);
 }
 
 template <typename S>
@@ -587,13 +587,13 @@ __global__ void __launch_bounds__(256) k_block_update_p(const BlockArgs b, Vec p
   const int blk = site < b.nsites ? b.be_blk[site] : -1;
   if (blk < 0) return;
   const R be = (R)scal[((size_t)blk * b.nrhs + r) * kScal + 2];
-  const size_t o = ((size_t)r * pv.stride + site) * Ls + s;
+  const size_t o = (size_t)r * pv.stride + site;
   R p[24], rr[24];
-  load24<R>(reinterpret_cast<const S *>(pv.data), pv.norm, o, p);
-  load24<R>(reinterpret_cast<const S *>(rv.data), rv.norm, o, rr);
+  load24<R>(reinterpret_cast<const S *>(pv.data), pv.norm, o, s, Ls, p);
+  load24<R>(reinterpret_cast<const S *>(rv.data), rv.norm, o, s, Ls, rr);
 #pragma unroll
   for (int k = 0; k < 24; ++k) p[k] = rr[k] + be * p[k];
-  store24<R>(reinterpret_cast<S *>(pv.data), pv.norm, o, p);
+  store24<R>(reinterpret_cast<S *>(pv.data), pv.norm, o, s, Ls, p);
 }
 
 // one thread per (block, rhs); sums that block's workgroup partials in order

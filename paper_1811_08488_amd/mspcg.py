@@ -123,8 +123,21 @@ class Action:
         return int(np.prod(self.L))
 
 
+def to_device_layout(a: np.ndarray) -> np.ndarray:
+    """complex128 [nrhs, sites, Ls, 4, 3] -> flat float64 in the F64 field layout
+    [rhs][site][chunk][s][2 reals] (12 chunks of 2 reals per 5D site)."""
+    nrhs, ns, Ls = a.shape[:3]
+    r = a.view(np.float64).reshape(nrhs, ns, Ls, 12, 2)
+    return np.ascontiguousarray(r.transpose(0, 1, 3, 2, 4)).reshape(-1)
+
+
+def from_device_layout(flat: np.ndarray, nrhs: int, ns: int, Ls: int) -> np.ndarray:
+    r = flat.reshape(nrhs, ns, 12, Ls, 2).transpose(0, 1, 3, 2, 4)
+    return np.ascontiguousarray(r).view(np.complex128).reshape(nrhs, ns, Ls, 4, 3)
+
+
 class Field:
-    """One parity of a 5D field in device memory: data [nrhs][V/2][Ls][24] (+ norm [nrhs][V/2][Ls])."""
+    """One parity of a 5D field in device memory (layout of include/mspcg.h) plus the F16/BF16 norms."""
 
     def __init__(self, data, norm, prec, nrhs, parity):
         self.data, self.norm, self.prec, self.nrhs, self.parity = data, norm, prec, nrhs, parity
@@ -189,7 +202,7 @@ class Handle:
         if a.ndim == 4:
             a = a[None]
         nrhs = a.shape[0]
-        f64 = Field(torch.from_numpy(a.view(np.float64).reshape(-1)).to("cuda"), None, F64, nrhs, parity)
+        f64 = Field(torch.from_numpy(to_device_layout(a)).to("cuda"), None, F64, nrhs, parity)
         if prec == F64:
             return f64
         out = self.field(prec, nrhs, parity)
@@ -204,8 +217,7 @@ class Handle:
             self.convert(t, f)
             f = t
         torch.cuda.synchronize()
-        a = f.data.cpu().numpy().view(np.complex128)
-        return a.reshape(f.nrhs, self.A.V // 2, self.A.Ls, 4, 3)
+        return from_device_layout(f.data.cpu().numpy(), f.nrhs, self.A.V // 2, self.A.Ls)
 
     # -------------------------------------------------------- operators
     def convert(self, out: Field, inp: Field, stream=None):
