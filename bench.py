@@ -121,6 +121,28 @@ def cpu_baseline(w, U, outer_iters, n_inner, nblk, budget_s=20.0):
     }
 
 
+def kernels_only(w, torch):
+    """dslash_eo in each storage precision, then a plain copy (F64 -> F64 conversion, which reads and
+    writes exactly one field) used to calibrate the HBM byte counters."""
+    eps = w.eps if w.eps is not None else synth.tuned_eps()
+    U = synth.gauge_field(w.L, eps, w.gauge_seed)
+    A = M.Action(w.L, w.Ls, M5=w.M5, mf=w.mf, b=w.b, c=w.c, t_bc=-1)
+    h = M.Handle(A, U)
+    src = h.upload(synth.cb_field(w.L, w.Ls, w.nrhs, 99), 1, M.F64)
+    for p in (M.F64, M.F32, M.F16):
+        fin, fout = h.field(p, w.nrhs, 1), h.field(p, w.nrhs, 0)
+        h.convert(fin, src)
+        for _ in range(10):
+            h.dslash_eo(fout, fin, 0)
+    dst = h.field(M.F64, w.nrhs, 1)
+    for _ in range(10):
+        h.convert(dst, src)
+    torch.cuda.synchronize()
+    field_bytes = (A.V // 2) * w.Ls * w.nrhs * 24 * 8
+    print(json.dumps({"kernels_only": w.name, "copy_bytes_read": field_bytes, "copy_bytes_written": field_bytes}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +153,9 @@ def main():
     ap.add_argument("--n-inner", type=int, default=None)
     ap.add_argument("--cg-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only launch dslash_eo (F64/F32/F16) and a plain F64 copy of the same size, 10 times each "
+                         "(the workload for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (the method's "
@@ -145,6 +170,9 @@ def main():
     inner_prec = PREC[args.inner_prec or w.inner_prec]
     k = args.n_inner if args.n_inner is not None else w.n_inner
     nblk = w.nblk
+    if args.kernels_only:
+        kernels_only(w, torch)
+        return
     h, A, U, eps, b = build_problem(w, torch)
     x = h.field(M.F64, w.nrhs, 0)
 

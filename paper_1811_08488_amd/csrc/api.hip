@@ -57,6 +57,8 @@ struct DBuf {
       fail(MSPCG_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");
     }
     bytes = n;
+    // new buffers start at zero (block lists rely on their never-written zero sites)
+    HIPCHK(hipMemset(p, 0, n));
   }
   template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
 };
@@ -103,21 +105,31 @@ struct BlockGeom {
 
 constexpr int kPad = 64;  // block lists are padded to multiples of this many sites
 
+// A dense fifth-dimension operator [2][Ls][Ls] in FP64 and FP32 (the compute
+// types of the kernels).
+struct Mat5 {
+  DBuf d, f;
+  const void *ptr(int prec) const { return prec == MSPCG_F64 ? d.p : f.p; }
+};
+
 }  // namespace
 
 struct mspcg_handle {
   mspcg_dwf par;
   int V = 0, Vh = 0, Lxyz = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;       // caller's stream given at creation (set-up work)
+  hipStream_t work = nullptr;         // the solvers' own stream (default priority, capturable)
+  // captured preconditioner launches, keyed by everything they bake in
+  std::map<std::vector<intptr_t>, hipGraphExec_t> graphs;
   double alpha5 = 0, beta5 = 0;  // M_5 = alpha5 - beta5 P_chi
   // global tables per parity: site list (identity), neighbours (cb of the other parity)
-  DBuf d_iota, d_nbr[2], d_lex[2], d_nbrlex[2];
+  DBuf d_order[2], d_nbr[2], d_lex[2], d_nbrlex[2];
   std::vector<int> lex_of_cb[2], nbr_cb[2];
   DBuf links[4][2];
   bool links_ok[4] = {false, false, false, false};
   DBuf d_gauge;
   // dense fifth-dimension matrices [2][Ls][Ls]
-  DBuf d_m5inv, d_m5inv_t, d_x1, d_x3;
+  Mat5 m5inv, m5inv_t, x1, x3;
   // FP64 workspaces
   OwnedVec tmp_o, tmp_e, tmp_o2, tmp_e2, sr, sp, sq, sz;
   DBuf partial, scal;
@@ -125,6 +137,11 @@ struct mspcg_handle {
   // sites per workgroup chosen by the autotuner, per kernel variant and shape
   std::map<std::vector<int>, int> tuned;
   bool autotune = true;
+  ~mspcg_handle() {
+    if (work) (void)hipStreamSynchronize(work);
+    for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
+    if (work) (void)hipStreamDestroy(work);
+  }
 };
 
 namespace {
@@ -262,9 +279,9 @@ HopArgs base_args(mspcg_handle *h, int nrhs) {
 // variant/shape times every candidate with HIP events on the stream (the
 // kernels are pure functions of their inputs, so repeating them is harmless)
 // and keeps the fastest; the default shape wins ties within 3%.
-int run_hop(mspcg_handle *h, int list_kind, int prec, int dag, int pre, int epi, int dot, HopArgs a,
+int run_hop(mspcg_handle *h, int list_kind, int prec, int dag, int pre, int epi, int dot, int global, HopArgs a,
             hipStream_t st) {
-  const std::vector<int> key = {list_kind, prec, dag, pre, epi, dot, a.Ls, a.nrhs, a.nsites};
+  const std::vector<int> key = {list_kind, prec, dag, pre, epi, dot, global, a.Ls, a.nrhs, a.nsites};
   auto it = h->tuned.find(key);
   int n = 0;
   if (it != h->tuned.end()) {
@@ -281,12 +298,12 @@ int run_hop(mspcg_handle *h, int list_kind, int prec, int dag, int pre, int epi,
         const int thr = c * a.nrhs * a.Ls;
         if (thr > 256 || (thr < 64 && 2 * thr <= 256 && c < kPad)) continue;
         a.nsite_wg = c;
-        if (launch_hop(prec, dag, pre, epi, dot, a, st) != hipSuccess) {
+        if (launch_hop(prec, dag, pre, epi, dot, global, a, st) != hipSuccess) {
           (void)hipGetLastError();
           continue;
         }
         HIPCHK(hipEventRecord(e0, st));
-        for (int rep = 0; rep < 3; ++rep) HIPCHK(launch_hop(prec, dag, pre, epi, dot, a, st));
+        for (int rep = 0; rep < 3; ++rep) HIPCHK(launch_hop(prec, dag, pre, epi, dot, global, a, st));
         HIPCHK(hipEventRecord(e1, st));
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0;
@@ -303,19 +320,20 @@ int run_hop(mspcg_handle *h, int list_kind, int prec, int dag, int pre, int epi,
     h->tuned[key] = n;
   }
   a.nsite_wg = n;
-  HIPCHK(launch_hop(prec, dag, pre, epi, dot, a, st));
+  HIPCHK(launch_hop(prec, dag, pre, epi, dot, global, a, st));
   return (a.nsites + n - 1) / n;
 }
 
 // Full-lattice hop: output parity p (site list = all cb), input parity 1-p.
 int global_hop(mspcg_handle *h, int prec, int nrhs, int p, const Vec &out, const Vec &in, int dag, int pre, int epi,
-               double scale, const double *mat, const Vec *other, double *partial, const Vec *dotw,
+               double scale, const Mat5 *mat, const Vec *other, double *partial, const Vec *dotw,
                hipStream_t st) {
   ensure_links(h, prec, st);
   HopArgs a = base_args(h, nrhs);
   a.nsites = h->Vh;
-  a.site_cb = h->d_iota.as<int>();
+  a.site_cb = h->d_order[p].as<int>();
   a.nbr = h->d_nbr[p].as<int>();
+  a.zero_site = 0;
   a.in = in.data;
   a.in_norm = in.norm;
   a.in_stride = h->Vh;
@@ -324,7 +342,7 @@ int global_hop(mspcg_handle *h, int prec, int nrhs, int p, const Vec &out, const
   a.out_stride = h->Vh;
   a.links = h->links[prec][p].p;
   a.scale = scale;
-  a.mat = mat;
+  a.mat = mat ? mat->ptr(prec) : nullptr;
   if (other) {
     a.other = other->data;
     a.other_norm = other->norm;
@@ -336,7 +354,7 @@ int global_hop(mspcg_handle *h, int prec, int nrhs, int p, const Vec &out, const
     a.dotw_norm = dotw->norm;
     a.dotw_stride = h->Vh;
   }
-  return run_hop(h, 0, prec, dag, pre, epi, partial ? 1 : 0, a, st);
+  return run_hop(h, 0, prec, dag, pre, epi, partial ? 1 : 0, 1, a, st);
 }
 
 // out_e = D_PC^+ D_PC in_e (all four hops fused with their fifth-dimension
@@ -344,11 +362,11 @@ int global_hop(mspcg_handle *h, int prec, int nrhs, int p, const Vec &out, const
 int apply_mdagm(mspcg_handle *h, int prec, int nrhs, const Vec &out, const Vec &in, const Vec &to, const Vec &te,
                 double *partial, hipStream_t st) {
   // c_o = M_phi M_5^{-1} (-1/2 H_oe M_phi in)
-  global_hop(h, prec, nrhs, 1, to, in, 0, 1, EPI_DENSE, -0.5, h->d_x1.as<double>(), nullptr, nullptr, nullptr, st);
+  global_hop(h, prec, nrhs, 1, to, in, 0, 1, EPI_DENSE, -0.5, &h->x1, nullptr, nullptr, nullptr, st);
   // y_e = M_5 in + 1/2 H_eo c_o  (= D_PC in)
   global_hop(h, prec, nrhs, 0, te, to, 0, 0, EPI_M5_OTHER, 0.5, nullptr, &in, nullptr, nullptr, st);
   // f_o = M_5^{-+} M_phi^+ (-1/2 H^+_oe y_e)
-  global_hop(h, prec, nrhs, 1, to, te, 1, 0, EPI_DENSE, -0.5, h->d_x3.as<double>(), nullptr, nullptr, nullptr, st);
+  global_hop(h, prec, nrhs, 1, to, te, 1, 0, EPI_DENSE, -0.5, &h->x3, nullptr, nullptr, nullptr, st);
   // out = M_5^+ y + 1/2 M_phi^+ H^+_eo f  (= D_PC^+ y)
   return global_hop(h, prec, nrhs, 0, out, to, 1, 0, EPI_M5DAG_MPHIDAG, 0.5, nullptr, &te, partial, &in, st);
 }
@@ -498,11 +516,20 @@ BlockGeom *get_blocks(mspcg_handle *h, const int nblk[4], hipStream_t st) {
   bg->be_tot = bg->be_off.back();
   bg->o1_tot = bg->o1_off.back();
   bg->e2_tot = bg->e2_off.back();
-  // every index must stay inside its list
-  for (int x : be_nbr) if (x >= bg->o1_tot) fail(MSPCG_EINVAL, "internal: B_e table out of range");
-  for (int x : e2_nbr) if (x >= bg->o1_tot) fail(MSPCG_EINVAL, "internal: E2 table out of range");
-  for (int x : o1_nbr_e2) if (x >= bg->e2_tot) fail(MSPCG_EINVAL, "internal: O1 table out of range");
-  for (int x : o1_nbr_be) if (x >= bg->be_tot) fail(MSPCG_EINVAL, "internal: O1 table out of range");
+  // a neighbour outside the domain (and every entry of a padding site) reads
+  // the target list's zero site, the first of its kPad extra sites
+  auto to_zero = [](std::vector<int> &t, int zero) {
+    for (int &x : t) {
+      if (x < 0) x = zero;
+      if (x > zero) fail(MSPCG_EINVAL, "internal: block table out of range");
+    }
+  };
+  to_zero(be_nbr, bg->o1_tot);
+  to_zero(e2_nbr, bg->o1_tot);
+  to_zero(o1_nbr_e2, bg->e2_tot);
+  to_zero(o1_nbr_be, bg->be_tot);
+  to_zero(e2_be, bg->be_tot);
+  to_zero(be_e2, bg->e2_tot);
   upload(bg->d_be_cb, be_cb, st);
   upload(bg->d_be_blk, be_blk, st);
   upload(bg->d_be_nbr, be_nbr, st);
@@ -522,26 +549,38 @@ BlockGeom *get_blocks(mspcg_handle *h, const int nblk[4], hipStream_t st) {
 
 void ensure_block_vecs(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs) {
   const int Ls = h->par.Ls;
-  bg->x.ensure(prec, nrhs, bg->be_tot, Ls);
-  bg->r.ensure(prec, nrhs, bg->be_tot, Ls);
-  bg->p.ensure(prec, nrhs, bg->be_tot, Ls);
-  bg->Ap.ensure(prec, nrhs, bg->be_tot, Ls);
-  bg->o1v.ensure(prec, nrhs, bg->o1_tot, Ls);
-  bg->e2v.ensure(prec, nrhs, bg->e2_tot, Ls);
+  const bool relayout = bg->vprec != prec || bg->vnrhs != nrhs;
+  // each list carries kPad extra sites after its last block: never written, so zero
+  bg->x.ensure(prec, nrhs, bg->be_tot + kPad, Ls);
+  bg->r.ensure(prec, nrhs, bg->be_tot + kPad, Ls);
+  bg->p.ensure(prec, nrhs, bg->be_tot + kPad, Ls);
+  bg->Ap.ensure(prec, nrhs, bg->be_tot + kPad, Ls);
+  bg->o1v.ensure(prec, nrhs, bg->o1_tot + kPad, Ls);
+  bg->e2v.ensure(prec, nrhs, bg->e2_tot + kPad, Ls);
   const int nwg = bg->be_tot;  // upper bound on workgroups (nsite_wg >= 1)
   bg->partial.ensure((size_t)nwg * nrhs * sizeof(double));
   bg->scal.ensure((size_t)bg->nb * nrhs * kScal * sizeof(double));
   bg->rrbuf.ensure((size_t)nrhs * sizeof(double) + 16);
+  if (relayout) {
+    // the zero sites sit at other byte offsets in another precision or nrhs:
+    // clear the buffers once so that they hold zeros again
+    for (OwnedVec *v : {&bg->x, &bg->r, &bg->p, &bg->Ap, &bg->o1v, &bg->e2v}) {
+      if (v->data.p) HIPCHK(hipMemset(v->data.p, 0, v->data.bytes));
+      if (v->norm.p) HIPCHK(hipMemset(v->norm.p, 0, v->norm.bytes));
+    }
+  }
   bg->vprec = prec;
   bg->vnrhs = nrhs;
 }
 
+// Block-domain hop: the input list's zero site is its first extra site.
 HopArgs block_hop_args(mspcg_handle *h, int nrhs, int nsites, const int *site_cb, const int *nbr, const Vec &in,
                        const Vec &out, int out_parity, int prec) {
   HopArgs a = base_args(h, nrhs);
   a.nsites = nsites;
   a.site_cb = site_cb;
   a.nbr = nbr;
+  a.zero_site = (int)(in.stride - kPad);
   a.in = in.data;
   a.in_norm = in.norm;
   a.in_stride = in.stride;
@@ -559,8 +598,8 @@ int block_hops(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, const Vec &in
   HopArgs a1 = block_hop_args(h, nrhs, bg->o1_tot, bg->d_o1_cb.as<int>(), bg->d_o1_nbr_be.as<int>(), in,
                               bg->o1v.v, 1, prec);
   a1.scale = -0.5;
-  a1.mat = h->d_x1.as<double>();
-  run_hop(h, 1, prec, 0, 1, EPI_DENSE, 0, a1, st);
+  a1.mat = h->x1.ptr(prec);
+  run_hop(h, 1, prec, 0, 1, EPI_DENSE, 0, 0, a1, st);
   HopArgs a2 = block_hop_args(h, nrhs, bg->e2_tot, bg->d_e2_cb.as<int>(), bg->d_e2_nbr.as<int>(), bg->o1v.v,
                               bg->e2v.v, 0, prec);
   a2.scale = 0.5;
@@ -568,12 +607,13 @@ int block_hops(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, const Vec &in
   a2.other_norm = in.norm;
   a2.other_stride = in.stride;
   a2.other_idx = bg->d_e2_be.as<int>();
-  run_hop(h, 2, prec, 0, 0, EPI_M5_OTHER, 0, a2, st);
+  a2.other_zero = bg->be_tot;
+  run_hop(h, 2, prec, 0, 0, EPI_M5_OTHER, 0, 0, a2, st);
   HopArgs a3 = block_hop_args(h, nrhs, bg->o1_tot, bg->d_o1_cb.as<int>(), bg->d_o1_nbr_e2.as<int>(), bg->e2v.v,
                               bg->o1v.v, 1, prec);
   a3.scale = -0.5;
-  a3.mat = h->d_x3.as<double>();
-  run_hop(h, 3, prec, 1, 0, EPI_DENSE, 0, a3, st);
+  a3.mat = h->x3.ptr(prec);
+  run_hop(h, 3, prec, 1, 0, EPI_DENSE, 0, 0, a3, st);
   HopArgs a4 = block_hop_args(h, nrhs, bg->be_tot, bg->d_be_cb.as<int>(), bg->d_be_nbr.as<int>(), bg->o1v.v, out,
                               0, prec);
   a4.scale = 0.5;
@@ -581,13 +621,14 @@ int block_hops(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, const Vec &in
   a4.other_norm = bg->e2v.v.norm;
   a4.other_stride = bg->e2v.v.stride;
   a4.other_idx = bg->d_be_e2.as<int>();
+  a4.other_zero = bg->e2_tot;
   if (partial) {
     a4.partial = partial;
     a4.dotw = in.data;
     a4.dotw_norm = in.norm;
     a4.dotw_stride = in.stride;
   }
-  const int grid = run_hop(h, 4, prec, 1, 0, EPI_M5DAG_MPHIDAG, partial ? 1 : 0, a4, st);
+  const int grid = run_hop(h, 4, prec, 1, 0, EPI_M5DAG_MPHIDAG, partial ? 1 : 0, 0, a4, st);
   return (bg->be_tot + grid - 1) / grid;  // sites per workgroup of the last hop
 }
 
@@ -654,7 +695,9 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
       if (pc->n_inner < 0) fail(MSPCG_EINVAL, "n_inner < 0");
       if (pc->inner_prec < MSPCG_F64 || pc->inner_prec > MSPCG_BF16) fail(MSPCG_EINVAL, "bad inner precision");
     }
-    hipStream_t st = h->stream;
+    // the caller's fields may still be written by work on other streams
+    HIPCHK(hipDeviceSynchronize());
+    hipStream_t st = h->work;
     const int nrhs = b->nrhs, Ls = h->par.Ls;
     const long long n = (long long)h->Vh * Ls * 24;
     BlockGeom *bg = pc ? get_blocks(h, pc->nblk, st) : nullptr;
@@ -701,14 +744,45 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
       norm2(rd, w.rr);
       to_host(w.rr, hr);
     };
+    auto precond_launch = [&] {
+      int nparts = 0;
+      run_block_cg(h, bg, pc->inner_prec, nrhs, pc->n_inner, Z, R, w.rr, part, &nparts, st);
+      HIPCHK(blas_reduce(part, nparts, nrhs, w.tmp, st));
+    };
     auto precond = [&] {  // z = M^{-1} r and rho_new = <z, r> into w.tmp
-      if (pc) {
-        int nparts = 0;
-        run_block_cg(h, bg, pc->inner_prec, nrhs, pc->n_inner, Z, R, w.rr, part, &nparts, st);
-        HIPCHK(blas_reduce(part, nparts, nrhs, w.tmp, st));
-      } else {
+      if (!pc) {
         HIPCHK(hipMemcpyAsync(w.tmp, w.rr, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
+        return;
       }
+      if (!s->use_graph) {
+        precond_launch();
+        return;
+      }
+      const std::vector<intptr_t> key = {(intptr_t)bg, pc->inner_prec, nrhs, pc->n_inner, (intptr_t)Z.data,
+                                         (intptr_t)R.data, (intptr_t)w.rr, (intptr_t)part, (intptr_t)w.tmp};
+      auto it = h->graphs.find(key);
+      if (it != h->graphs.end()) {
+        HIPCHK(hipGraphLaunch(it->second, st));
+        return;
+      }
+      // first use: run eagerly (tunes launch shapes and sizes every buffer), then
+      // capture the identical launch sequence for the following iterations
+      precond_launch();
+      hipGraph_t graph = nullptr;
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      try {
+        precond_launch();
+      } catch (...) {
+        (void)hipStreamEndCapture(st, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+      }
+      HIPCHK(hipStreamEndCapture(st, &graph));
+      hipGraphExec_t exec = nullptr;
+      const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HIPCHK(e);
+      h->graphs[key] = exec;
     };
     const double tol2 = s->tol * s->tol;
     norm2(bd, w.bb);
@@ -809,6 +883,7 @@ mspcg_status mspcg_create(mspcg_handle **hp, const mspcg_dwf *p, const double *g
     h->Vh = (int)(V / 2);
     h->Lxyz = p->L[0] * p->L[1] * p->L[2];
     h->stream = S(stream);
+    HIPCHK(hipStreamCreateWithFlags(&h->work, hipStreamNonBlocking));
     if (const char *e = std::getenv("MSPCG_AUTOTUNE")) h->autotune = std::atoi(e) != 0;
     h->alpha5 = p->b * (4.0 - p->M5) + 1.0;
     h->beta5 = 1.0 - p->c * (4.0 - p->M5);
@@ -819,9 +894,25 @@ mspcg_status mspcg_create(mspcg_handle **hp, const mspcg_dwf *p, const double *g
     // index maps
     const int *L = p->L;
     const int Lxh = L[0] / 2;
-    std::vector<int> iota(h->Vh);
-    for (int i = 0; i < h->Vh; ++i) iota[i] = i;
-    upload(h->d_iota, iota, st);
+    // output sites of the full-lattice hop are visited in 4D tiles (extent 4
+    // where it divides the lattice, else 2) so that a tile's neighbours stay in cache
+    int tdim[4];
+    for (int mu = 0; mu < 4; ++mu) tdim[mu] = (L[mu] % 4 == 0) ? 4 : 2;
+    for (int par = 0; par < 2; ++par) {
+      std::vector<int> order;
+      order.reserve(h->Vh);
+      for (int bt = 0; bt < L[3]; bt += tdim[3])
+        for (int bz = 0; bz < L[2]; bz += tdim[2])
+          for (int by = 0; by < L[1]; by += tdim[1])
+            for (int bx = 0; bx < L[0]; bx += tdim[0])
+              for (int t = bt; t < bt + tdim[3]; ++t)
+                for (int z = bz; z < bz + tdim[2]; ++z)
+                  for (int y = by; y < by + tdim[1]; ++y)
+                    for (int x = bx; x < bx + tdim[0]; ++x)
+                      if (((x + y + z + t) & 1) == par) order.push_back((x + L[0] * (y + L[1] * (z + L[2] * t))) >> 1);
+      if ((int)order.size() != h->Vh) fail(MSPCG_EINVAL, "internal: tile order incomplete");
+      upload(h->d_order[par], order, st);
+    }
     for (int par = 0; par < 2; ++par) {
       auto &lex = h->lex_of_cb[par];
       auto &nbr = h->nbr_cb[par];
@@ -859,10 +950,14 @@ mspcg_status mspcg_create(mspcg_handle **hp, const mspcg_dwf *p, const double *g
     Mat pp = mphi_chiral(Ls, p->b, p->c, p->mf, false);
     Mat pm = mphi_chiral(Ls, p->b, p->c, p->mf, true);
     Mat x1p = matmul(pp, ip, Ls), x1m = matmul(pm, im, Ls);
-    upload(h->d_m5inv, pack2(ip, im), st);
-    upload(h->d_m5inv_t, pack2(transpose(ip, Ls), transpose(im, Ls)), st);
-    upload(h->d_x1, pack2(x1p, x1m), st);
-    upload(h->d_x3, pack2(transpose(x1p, Ls), transpose(x1m, Ls)), st);
+    auto up5 = [&](Mat5 &m, const std::vector<double> &v) {
+      upload(m.d, v, st);
+      upload(m.f, std::vector<float>(v.begin(), v.end()), st);
+    };
+    up5(h->m5inv, pack2(ip, im));
+    up5(h->m5inv_t, pack2(transpose(ip, Ls), transpose(im, Ls)));
+    up5(h->x1, pack2(x1p, x1m));
+    up5(h->x3, pack2(transpose(x1p, Ls), transpose(x1m, Ls)));
     HIPCHK(hipStreamSynchronize(st));
   });
   if (rc == MSPCG_OK) *hp = h.release();
@@ -913,7 +1008,7 @@ mspcg_status m5inv(mspcg_handle *h, mspcg_field *out, const mspcg_field *in, int
     a.out_norm = out->norm;
     a.stride = h->Vh;
     a.dense = 1;
-    a.mat = dagger ? h->d_m5inv_t.as<double>() : h->d_m5inv.as<double>();
+    a.mat = dagger ? h->m5inv_t.ptr(in->prec) : h->m5inv.ptr(in->prec);
     HIPCHK(launch_op5(in->prec, a, S(stream)));
   });
 }
@@ -998,13 +1093,13 @@ mspcg_status dwf_prepare_rhs(mspcg_handle *h, mspcg_field *b, const mspcg_field 
     a.out = to.data;
     a.stride = h->Vh;
     a.dense = 1;
-    a.mat = h->d_m5inv.as<double>();
+    a.mat = h->m5inv.ptr(MSPCG_F64);
     HIPCHK(launch_op5(MSPCG_F64, a, st));
     // te = M^4_eo t_o ; phihat = phi_e - te (into te)
     global_hop(h, MSPCG_F64, nrhs, 0, te, to, 0, 1, EPI_SCALE, -0.5, nullptr, nullptr, nullptr, nullptr, st);
     HIPCHK(blas_axpby((double *)te.data, 1.0, (const double *)phi_e->data, -1.0, (const double *)te.data, n, nrhs, st));
     // b = D_PC^+ phihat
-    global_hop(h, MSPCG_F64, nrhs, 1, to, te, 1, 0, EPI_DENSE, -0.5, h->d_x3.as<double>(), nullptr, nullptr, nullptr,
+    global_hop(h, MSPCG_F64, nrhs, 1, to, te, 1, 0, EPI_DENSE, -0.5, &h->x3, nullptr, nullptr, nullptr,
                st);
     global_hop(h, MSPCG_F64, nrhs, 0, vec_of(h, b), to, 1, 0, EPI_M5DAG_MPHIDAG, 0.5, nullptr, &te, nullptr, nullptr,
                st);
@@ -1042,7 +1137,7 @@ mspcg_status dwf_reconstruct(mspcg_handle *h, mspcg_field *psi_o, const mspcg_fi
     a.out = psi_o->data;
     a.stride = h->Vh;
     a.dense = 1;
-    a.mat = h->d_m5inv.as<double>();
+    a.mat = h->m5inv.ptr(MSPCG_F64);
     HIPCHK(launch_op5(MSPCG_F64, a, st));
     HIPCHK(hipStreamSynchronize(st));
   });

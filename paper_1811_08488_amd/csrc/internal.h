@@ -30,7 +30,9 @@ struct HopArgs {
   int nsites;          // output list length
   int Ls, nrhs, nsite_wg;
   const int *site_cb;  // [nsites] cb of the output site in the full lattice (-1: padding)
-  const int *nbr;      // [nsites][8] input-list index of neighbour d = 2 mu + (0 fwd, 1 bwd), -1: zero
+  const int *nbr;      // [site][8] input index of neighbour d = 2 mu + (0 fwd, 1 bwd); indexed by cb for the
+                       // full lattice, by list position for block domains (outside: the input's zero site)
+  int zero_site;       // input index read by inactive threads (an all-zero site of block lists)
   const void *in;
   const float *in_norm;
   long long in_stride;
@@ -41,9 +43,10 @@ struct HopArgs {
   const void *other;   // EPI_M5_OTHER / EPI_M5DAG_MPHIDAG operand
   const float *other_norm;
   long long other_stride;
-  const int *other_idx;  // output site -> index in `other` (-1: zero); nullptr: identity
+  const int *other_idx;  // output list position -> index in `other`; nullptr: identity
+  int other_zero;        // zero site of `other` (inactive threads)
   double scale;
-  const double *mat;   // EPI_DENSE: [2][Ls][Ls] row-major (chirality +, then -)
+  const void *mat;     // EPI_DENSE: [2][Ls][Ls] row-major (chirality +, then -) in the compute type
   double mphi_b, mphi_c, mf, m5_alpha, m5_beta;
   double *partial;     // DOT: [gridDim.x][nrhs] partial sums of Re<w, out>
   const void *dotw;
@@ -52,7 +55,8 @@ struct HopArgs {
 };
 
 // Launch the hop kernel for storage `prec`; returns hipSuccess or the launch error.
-hipError_t launch_hop(int prec, int dagger, int pre_mphi, int epi, int dot, const HopArgs &a, hipStream_t st);
+hipError_t launch_hop(int prec, int dagger, int pre_mphi, int epi, int dot, int global, const HopArgs &a,
+                      hipStream_t st);
 
 // out = X in on a site list (identity list), X = a + b P_chi (dag: P_chi^+) or a dense chiral matrix.
 struct Op5Args {
@@ -63,7 +67,7 @@ struct Op5Args {
   float *out_norm;
   long long stride;
   int dense;            // 1: use mat; 0: a + b P_chi
-  const double *mat;    // [2][Ls][Ls]
+  const void *mat;      // [2][Ls][Ls] row-major in the compute type
   double a, b, mf;
   int dag;
 };

@@ -46,26 +46,89 @@ __device__ inline void pchi_comb(R *lds, int nthr, int tid, int s, int Ls, R a, 
   for (int k = 12; k < 24; ++k) v[k] = a * v[k] + cl * lds[k * nthr + tl];
 }
 
-// v <- X v with X real Ls x Ls per chirality (matT[chi][t][s] in LDS, transposed).
+// ---------------------------------------------------------------- dense fifth-dimension matrices
+// v <- scale * X v, X a real Ls x Ls matrix per chirality (rows s, columns t;
+// chirality + acts on reals 0..11, chirality - on 12..23).  The Ls values of
+// one 4D site and right-hand side live on Ls consecutive lanes, so per
+// chirality this is X (Ls x Ls) times a (Ls x 12 n_groups) matrix: a dense
+// contraction that runs on the matrix cores (16x16x4 MFMA, FP32 or FP64
+// operands).  Needs a multiple of 64 threads and Ls % 4 == 0; otherwise the
+// VALU loop below is used.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <typename R> struct V4;
+template <> struct V4<float> { using T = f32x4; };
+template <> struct V4<double> { using T = f64x4; };
+__device__ inline f32x4 mfma16x16x4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline f64x4 mfma16x16x4(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// lds: [24][nthr] structure of arrays; X: [2][Ls][Ls] (LDS copy).  Lane l of a
+// wave supplies A[l%16][l/16] and B[l/16][l%16] and receives four entries of
+// column l%16 of D.
 template <typename R>
-__device__ inline void dense_chiral(R *lds, const R *matT, int nthr, int tid, int s, int Ls, R scale, R v[24]) {
+__device__ inline void dense_chiral(R *lds, const R *X, int nthr, int tid, int s, int Ls, int ngroups, R scale,
+                                   R v[24]) {
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 24; ++k) lds[k * nthr + tid] = v[k];
   __syncthreads();
-  const int g0 = tid - s;
-  R o[24];
-  zero24(o);
-  for (int t = 0; t < Ls; ++t) {
-    const R mp = matT[t * Ls + s];
-    const R mm = matT[Ls * Ls + t * Ls + s];
+  if ((nthr & 63) == 0 && (Ls & 3) == 0 && Ls <= 32) {
+    using T4 = typename V4<R>::T;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+    const int row = lane & 15, kq = lane >> 4;
+    const int ncol = ngroups * 12;
+    const int ntn = (ncol + 15) >> 4;
+    for (int task = wave; task < 2 * ntn; task += nwaves) {
+      const int chi = task / ntn, nt = task - chi * ntn;
+      const int col = nt * 16 + row;
+      const bool colok = col < ncol;
+      const int g = colok ? col / 12 : 0;
+      const int comp = chi * 12 + (colok ? col - 12 * g : 0);
+      const R *Xc = X + chi * Ls * Ls;
+      T4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+      for (int k0 = 0; k0 < Ls; k0 += 4) {
+        const int t = k0 + kq;
+        const R b = colok ? lds[comp * nthr + g * Ls + t] : R(0);
+        const R a0 = (row < Ls) ? Xc[row * Ls + t] : R(0);
+        c0 = mfma16x16x4(a0, b, c0);
+        if (Ls > 16) {
+          const R a1 = (16 + row < Ls) ? Xc[(16 + row) * Ls + t] : R(0);
+          c1 = mfma16x16x4(a1, b, c1);
+        }
+      }
+      if (colok) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) o[k] += mp * lds[k * nthr + g0 + t];
+        for (int i = 0; i < 4; ++i) {
+          // output rows of the 16x16x4 MFMA: FP32 puts rows 4(l/16)+i in lane l's
+          // four results, FP64 rows 4i + l/16
+          const int m = (sizeof(R) == 8) ? 4 * i + kq : 4 * kq + i;
+          if (m < Ls) lds[comp * nthr + g * Ls + m] = scale * c0[i];
+          if (Ls > 16 && 16 + m < Ls) lds[comp * nthr + g * Ls + 16 + m] = scale * c1[i];
+        }
+      }
+    }
+    __syncthreads();
 #pragma unroll
-    for (int k = 12; k < 24; ++k) o[k] += mm * lds[k * nthr + g0 + t];
+    for (int k = 0; k < 24; ++k) v[k] = lds[k * nthr + tid];
+  } else {
+    const int g0 = tid - s;
+    R o[24];
+    zero24(o);
+    for (int t = 0; t < Ls; ++t) {
+      const R mp = X[s * Ls + t];
+      const R mm = X[Ls * Ls + s * Ls + t];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) o[k] += mp * lds[k * nthr + g0 + t];
+#pragma unroll
+      for (int k = 12; k < 24; ++k) o[k] += mm * lds[k * nthr + g0 + t];
+    }
+#pragma unroll
+    for (int k = 0; k < 24; ++k) v[k] = scale * o[k];
   }
-#pragma unroll
-  for (int k = 0; k < 24; ++k) v[k] = scale * o[k];
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
@@ -102,75 +165,71 @@ __device__ inline void wg_partial(double *ldsd, int nthr, int tid, int Ls, int n
 // out(x) = epilogue( sum_mu [ P^{SGN_f}_mu U_mu(x) phi(x+mu) + P^{SGN_b}_mu U_mu(x-mu)^+ phi(x-mu) ] )
 // with phi = M_phi in (PRE) or in; SGN_f = +1, SGN_b = -1 for H and the reverse
 // for the daggered hop g5 H g5 = H^+.
-template <typename S, int DAG, int PRE, int EPI, int DOT>
+// Workgroup = (s, rhs, site) threads: threadIdx.x = s, .y = rhs, .z = site.
+// GLOBAL: the output list is the whole parity (site_cb a permutation of cb in
+// 4D-tile order); neighbour tables, outputs and the `other`/dot operands are
+// indexed by cb.  Otherwise (block domains) they are indexed by the position
+// in the list, and neighbours outside the domain point at the input list's
+// zero site, which is never written.
+template <typename S, int DAG, int PRE, int EPI, int DOT, int GLOBAL>
 __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
   using R = typename Traits<S>::R;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int nthr = blockDim.x;
+  const int Ls = a.Ls, nrhs = a.nrhs;
+  const int s = threadIdx.x, r = threadIdx.y, sl = threadIdx.z;
+  const int nthr = Ls * nrhs * a.nsite_wg;
+  const int tid = s + Ls * (r + nrhs * sl);
   R *lds = reinterpret_cast<R *>(smem);
-  R *matT = lds + 24 * nthr;
-  const int tid = threadIdx.x;
-  const int Ls = a.Ls;
-  const int G = a.nrhs * Ls;
-  const int sl = tid / G;
-  const int rem = tid - sl * G;
-  const int r = rem / Ls;
-  const int s = rem - r * Ls;
+  R *Xl = lds + 24 * nthr;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int site = tile * a.nsite_wg + sl;
-  const int cb = (site < a.nsites) ? a.site_cb[site] : -1;
-  const bool active = cb >= 0;
+  const int cbr = (site < a.nsites) ? a.site_cb[site] : -1;
+  const bool active = cbr >= 0;
+  const int cb = active ? cbr : 0;
+  const int self = GLOBAL ? cb : site;  // index of this site in tables and outputs
 
   if (EPI == EPI_DENSE) {
-    for (int i = tid; i < 2 * Ls * Ls; i += nthr) {
-      const int chi = i / (Ls * Ls), t = (i / Ls) % Ls, so = i % Ls;  // matT[chi][t][so] = mat[chi][so][t]
-      matT[i] = (R)a.mat[chi * Ls * Ls + so * Ls + t];
-    }
+    const R *Xg = reinterpret_cast<const R *>(a.mat);
+    for (int i = tid; i < 2 * Ls * Ls; i += nthr) Xl[i] = Xg[i];
   }
 
   const S *in = reinterpret_cast<const S *>(a.in);
   const S *links = reinterpret_cast<const S *>(a.links);
+  const int *nb = a.nbr + (size_t)(active ? self : 0) * 8;
+  const size_t rin = (size_t)r * a.in_stride;
   R acc[24];
   zero24(acc);
 
-#pragma unroll
+  // kept rolled: unrolling lets the compiler hoist all eight directions'
+  // loads, which exhausts the register file
+#pragma unroll 1
   for (int d = 0; d < 8; ++d) {
-    const int j = active ? a.nbr[(size_t)site * 8 + d] : -1;
-    R v[24];
-    if (j >= 0)
-      load24<R>(in, a.in_norm, (size_t)r * a.in_stride + j, s, Ls, v);
-    else
-      zero24(v);
+    const int j = active ? nb[d] : a.zero_site;
+    R v[24], u[18], h[12], w[12];
+    load24<R>(in, a.in_norm, rin + j, s, Ls, v);
+    load18<R>(links, (size_t)cb * 8 + d, u);
     if (PRE) pchi_comb<R>(lds, nthr, tid, s, Ls, (R)a.mphi_b, (R)a.mphi_c, (R)a.mf, 0, v);
-    if (j >= 0) {
-      R u[18], h[12], w[12];
-      load18<R>(links, (size_t)cb * 8 + d, u);
-      const int mu = d >> 1;
-      const bool bw = d & 1;
-      // SGN = +1 selects (1 - g_mu): forward for H, backward for H^+
-      const bool plus = (bw == (DAG != 0));
-      if (mu == 0) {
-        if (plus) { project<0, 1>(v, h); link_mul(u, h, w); accumulate<0, 1>(acc, w); }
-        else      { project<0, -1>(v, h); link_mul(u, h, w); accumulate<0, -1>(acc, w); }
-      } else if (mu == 1) {
-        if (plus) { project<1, 1>(v, h); link_mul(u, h, w); accumulate<1, 1>(acc, w); }
-        else      { project<1, -1>(v, h); link_mul(u, h, w); accumulate<1, -1>(acc, w); }
-      } else if (mu == 2) {
-        if (plus) { project<2, 1>(v, h); link_mul(u, h, w); accumulate<2, 1>(acc, w); }
-        else      { project<2, -1>(v, h); link_mul(u, h, w); accumulate<2, -1>(acc, w); }
-      } else {
-        if (plus) { project<3, 1>(v, h); link_mul(u, h, w); accumulate<3, 1>(acc, w); }
-        else      { project<3, -1>(v, h); link_mul(u, h, w); accumulate<3, -1>(acc, w); }
-      }
+    const int mu = d >> 1;
+    // SGN = +1 selects (1 - g_mu): forward for H, backward for H^+
+    const bool plus = ((d & 1) != 0) == (DAG != 0);
+    if (mu == 0) {
+      if (plus) { project<0, 1>(v, h); link_mul(u, h, w); accumulate<0, 1>(acc, w); }
+      else      { project<0, -1>(v, h); link_mul(u, h, w); accumulate<0, -1>(acc, w); }
+    } else if (mu == 1) {
+      if (plus) { project<1, 1>(v, h); link_mul(u, h, w); accumulate<1, 1>(acc, w); }
+      else      { project<1, -1>(v, h); link_mul(u, h, w); accumulate<1, -1>(acc, w); }
+    } else if (mu == 2) {
+      if (plus) { project<2, 1>(v, h); link_mul(u, h, w); accumulate<2, 1>(acc, w); }
+      else      { project<2, -1>(v, h); link_mul(u, h, w); accumulate<2, -1>(acc, w); }
+    } else {
+      if (plus) { project<3, 1>(v, h); link_mul(u, h, w); accumulate<3, 1>(acc, w); }
+      else      { project<3, -1>(v, h); link_mul(u, h, w); accumulate<3, -1>(acc, w); }
     }
   }
 
   const R scale = (R)a.scale;
-  if (EPI == EPI_SCALE) {
-#pragma unroll
-    for (int k = 0; k < 24; ++k) acc[k] *= scale;
-  } else if (EPI == EPI_DENSE) {
-    dense_chiral<R>(lds, matT, nthr, tid, s, Ls, scale, acc);
+  if (EPI == EPI_DENSE) {
+    dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * a.nsite_wg, scale, acc);
   } else if (EPI == EPI_MPHIDAG || EPI == EPI_M5DAG_MPHIDAG) {
     pchi_comb<R>(lds, nthr, tid, s, Ls, (R)a.mphi_b, (R)a.mphi_c, (R)a.mf, 1, acc);
 #pragma unroll
@@ -180,31 +239,28 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     for (int k = 0; k < 24; ++k) acc[k] *= scale;
   }
   if (EPI == EPI_M5_OTHER || EPI == EPI_M5DAG_MPHIDAG) {
-    const int oi = active ? (a.other_idx ? a.other_idx[site] : site) : -1;
+    const int oi = GLOBAL ? cb : (active ? (a.other_idx ? a.other_idx[site] : site) : a.other_zero);
     R o[24];
-    if (oi >= 0)
-      load24<R>(reinterpret_cast<const S *>(a.other), a.other_norm, (size_t)r * a.other_stride + oi, s, Ls, o);
-    else
-      zero24(o);
+    load24<R>(reinterpret_cast<const S *>(a.other), a.other_norm, (size_t)r * a.other_stride + oi, s, Ls, o);
     // M_5 = alpha - beta P_chi ; M_5^+ = alpha - beta P_chi^+
     pchi_comb<R>(lds, nthr, tid, s, Ls, (R)a.m5_alpha, (R)(-a.m5_beta), (R)a.mf, EPI == EPI_M5DAG_MPHIDAG, o);
 #pragma unroll
     for (int k = 0; k < 24; ++k) acc[k] += o[k];
   }
 
-  if (active) store24<R>(reinterpret_cast<S *>(a.out), a.out_norm, (size_t)r * a.out_stride + site, s, Ls, acc);
+  if (active) store24<R>(reinterpret_cast<S *>(a.out), a.out_norm, (size_t)r * a.out_stride + self, s, Ls, acc);
 
   if (DOT) {
     double val = 0;
     if (active) {
       R w[24];
-      load24<R>(reinterpret_cast<const S *>(a.dotw), a.dotw_norm, (size_t)r * a.dotw_stride + site, s, Ls, w);
+      load24<R>(reinterpret_cast<const S *>(a.dotw), a.dotw_norm, (size_t)r * a.dotw_stride + self, s, Ls, w);
       R t = 0;
 #pragma unroll
       for (int k = 0; k < 24; ++k) t += w[k] * acc[k];
       val = (double)t;
     }
-    wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, a.nrhs, a.nsite_wg, val, a.partial, tile);
+    wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, nrhs, a.nsite_wg, val, a.partial, tile);
   }
 }
 
@@ -217,39 +273,44 @@ static size_t hop_lds_bytes(const HopArgs &a, int nthr, int epi, int dot) {
   return b;
 }
 
-template <typename S, int DAG, int PRE, int EPI, int DOT>
+template <typename S, int DAG, int PRE, int EPI, int DOT, int GLOBAL>
 static hipError_t launch_hop_t(const HopArgs &a, hipStream_t st) {
   const int nthr = a.nsite_wg * a.nrhs * a.Ls;
   const int grid = (a.nsites + a.nsite_wg - 1) / a.nsite_wg;
   if (nthr < 1 || nthr > 256 || grid < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((hop_kernel<S, DAG, PRE, EPI, DOT>), dim3(grid), dim3(nthr), hop_lds_bytes<S>(a, nthr, EPI, DOT),
-                     st, a);
+  hipLaunchKernelGGL((hop_kernel<S, DAG, PRE, EPI, DOT, GLOBAL>), dim3(grid), dim3(a.Ls, a.nrhs, a.nsite_wg),
+                     hop_lds_bytes<S>(a, nthr, EPI, DOT), st, a);
   return hipGetLastError();
 }
 
 template <typename S>
-static hipError_t dispatch_hop(int dagger, int pre, int epi, int dot, const HopArgs &a, hipStream_t st) {
+static hipError_t dispatch_hop(int dagger, int pre, int epi, int dot, int global, const HopArgs &a, hipStream_t st) {
   // the combinations used by the operators (anything else is rejected)
-#define MSPCG_HOP(D, P, E, T) \
-  if (dagger == D && pre == P && epi == E && dot == T) return launch_hop_t<S, D, P, E, T>(a, st);
-  MSPCG_HOP(0, 1, EPI_SCALE, 0)          // M^4 in
-  MSPCG_HOP(1, 0, EPI_MPHIDAG, 0)        // (M^4)^+ in
-  MSPCG_HOP(0, 1, EPI_DENSE, 0)          // M_phi M_5^-1 M^4 in (first hop of D_PC)
-  MSPCG_HOP(0, 0, EPI_M5_OTHER, 0)       // M_5 psi + 1/2 H c
-  MSPCG_HOP(1, 0, EPI_DENSE, 0)          // M_5^-+ (M^4)^+ y
-  MSPCG_HOP(1, 0, EPI_M5DAG_MPHIDAG, 0)  // M_5^+ y + 1/2 M_phi^+ H^+ f
-  MSPCG_HOP(1, 0, EPI_M5DAG_MPHIDAG, 1)  //   ... with the fused <w, out>
-  MSPCG_HOP(0, 1, EPI_DENSE, 1)
+#define MSPCG_HOP(D, P, E, T, G)                                                \
+  if (dagger == D && pre == P && epi == E && dot == T && (global != 0) == (G != 0)) \
+    return launch_hop_t<S, D, P, E, T, G>(a, st);
+  MSPCG_HOP(0, 1, EPI_SCALE, 0, 1)          // M^4 in
+  MSPCG_HOP(1, 0, EPI_MPHIDAG, 0, 1)        // (M^4)^+ in
+  MSPCG_HOP(0, 1, EPI_DENSE, 0, 1)          // M_phi M_5^-1 M^4 in (first hop of D_PC)
+  MSPCG_HOP(0, 0, EPI_M5_OTHER, 0, 1)       // M_5 psi + 1/2 H c
+  MSPCG_HOP(1, 0, EPI_DENSE, 0, 1)          // M_5^-+ (M^4)^+ y
+  MSPCG_HOP(1, 0, EPI_M5DAG_MPHIDAG, 0, 1)  // M_5^+ y + 1/2 M_phi^+ H^+ f
+  MSPCG_HOP(1, 0, EPI_M5DAG_MPHIDAG, 1, 1)  //   ... with the fused <w, out>
+  MSPCG_HOP(0, 1, EPI_DENSE, 0, 0)          // the same four hops on block domains
+  MSPCG_HOP(0, 0, EPI_M5_OTHER, 0, 0)
+  MSPCG_HOP(1, 0, EPI_DENSE, 0, 0)
+  MSPCG_HOP(1, 0, EPI_M5DAG_MPHIDAG, 0, 0)
+  MSPCG_HOP(1, 0, EPI_M5DAG_MPHIDAG, 1, 0)
 #undef MSPCG_HOP
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_hop(int prec, int dagger, int pre, int epi, int dot, const HopArgs &a, hipStream_t st) {
+hipError_t launch_hop(int prec, int dagger, int pre, int epi, int dot, int global, const HopArgs &a, hipStream_t st) {
   switch (prec) {
-    case MSPCG_F64: return dispatch_hop<double>(dagger, pre, epi, dot, a, st);
-    case MSPCG_F32: return dispatch_hop<float>(dagger, pre, epi, dot, a, st);
-    case MSPCG_F16: return dispatch_hop<_Float16>(dagger, pre, epi, dot, a, st);
-    case MSPCG_BF16: return dispatch_hop<bf16>(dagger, pre, epi, dot, a, st);
+    case MSPCG_F64: return dispatch_hop<double>(dagger, pre, epi, dot, global, a, st);
+    case MSPCG_F32: return dispatch_hop<float>(dagger, pre, epi, dot, global, a, st);
+    case MSPCG_F16: return dispatch_hop<_Float16>(dagger, pre, epi, dot, global, a, st);
+    case MSPCG_BF16: return dispatch_hop<bf16>(dagger, pre, epi, dot, global, a, st);
   }
   return hipErrorInvalidValue;
 }
@@ -259,26 +320,23 @@ template <typename S>
 __global__ void __launch_bounds__(256) op5_kernel(const Op5Args a) {
   using R = typename Traits<S>::R;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int nthr = blockDim.x;
+  const int Ls = a.Ls, nrhs = a.nrhs;
+  const int s = threadIdx.x, r = threadIdx.y, sl = threadIdx.z;
+  const int nthr = Ls * nrhs * a.nsite_wg;
+  const int tid = s + Ls * (r + nrhs * sl);
   R *lds = reinterpret_cast<R *>(smem);
-  R *matT = lds + 24 * nthr;
-  const int tid = threadIdx.x, Ls = a.Ls, G = a.nrhs * Ls;
-  const int sl = tid / G, rem = tid - sl * G, r = rem / Ls, s = rem - r * Ls;
+  R *Xl = lds + 24 * nthr;
   const int site = blockIdx.x * a.nsite_wg + sl;
   const bool active = site < a.nsites;
-  if (a.dense)
-    for (int i = tid; i < 2 * Ls * Ls; i += nthr) {
-      const int chi = i / (Ls * Ls), t = (i / Ls) % Ls, so = i % Ls;
-      matT[i] = (R)a.mat[chi * Ls * Ls + so * Ls + t];
-    }
+  if (a.dense) {
+    const R *Xg = reinterpret_cast<const R *>(a.mat);
+    for (int i = tid; i < 2 * Ls * Ls; i += nthr) Xl[i] = Xg[i];
+  }
   R v[24];
-  const size_t idx = (size_t)r * a.stride + site;
-  if (active)
-    load24<R>(reinterpret_cast<const S *>(a.in), a.in_norm, idx, s, Ls, v);
-  else
-    zero24(v);
+  const size_t idx = (size_t)r * a.stride + (active ? site : 0);
+  load24<R>(reinterpret_cast<const S *>(a.in), a.in_norm, idx, s, Ls, v);
   if (a.dense)
-    dense_chiral<R>(lds, matT, nthr, tid, s, Ls, R(1), v);
+    dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * a.nsite_wg, R(1), v);
   else
     pchi_comb<R>(lds, nthr, tid, s, Ls, (R)a.a, (R)a.b, (R)a.mf, a.dag, v);
   if (active) store24<R>(reinterpret_cast<S *>(a.out), a.out_norm, idx, s, Ls, v);
@@ -290,11 +348,12 @@ hipError_t launch_op5(int prec, const Op5Args &a, hipStream_t st) {
   if (nthr < 1 || nthr > 256 || grid < 1) return hipErrorInvalidValue;
   const size_t rsz = (prec == MSPCG_F64) ? 8 : 4;
   const size_t lds = (24 * (size_t)nthr + 2 * (size_t)a.Ls * a.Ls) * rsz;
+  const dim3 blk(a.Ls, a.nrhs, a.nsite_wg);
   switch (prec) {
-    case MSPCG_F64: hipLaunchKernelGGL(op5_kernel<double>, dim3(grid), dim3(nthr), lds, st, a); break;
-    case MSPCG_F32: hipLaunchKernelGGL(op5_kernel<float>, dim3(grid), dim3(nthr), lds, st, a); break;
-    case MSPCG_F16: hipLaunchKernelGGL(op5_kernel<_Float16>, dim3(grid), dim3(nthr), lds, st, a); break;
-    case MSPCG_BF16: hipLaunchKernelGGL(op5_kernel<bf16>, dim3(grid), dim3(nthr), lds, st, a); break;
+    case MSPCG_F64: hipLaunchKernelGGL(op5_kernel<double>, dim3(grid), blk, lds, st, a); break;
+    case MSPCG_F32: hipLaunchKernelGGL(op5_kernel<float>, dim3(grid), blk, lds, st, a); break;
+    case MSPCG_F16: hipLaunchKernelGGL(op5_kernel<_Float16>, dim3(grid), blk, lds, st, a); break;
+    case MSPCG_BF16: hipLaunchKernelGGL(op5_kernel<bf16>, dim3(grid), blk, lds, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -596,16 +655,24 @@ __global__ void __launch_bounds__(256) k_block_update_p(const BlockArgs b, Vec p
   store24<R>(reinterpret_cast<S *>(pv.data), pv.norm, o, s, Ls, p);
 }
 
-// one thread per (block, rhs); sums that block's workgroup partials in order
-__global__ void k_block_scalars(int mode, int nblocks, int nrhs, int nsite_wg, const int *be_off,
-                                const double *partial, double *scal) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nblocks * nrhs) return;
-  const int blk = i / nrhs, r = i % nrhs;
+// one workgroup per (block, rhs): a fixed-shape tree sum of that block's
+// workgroup partials (deterministic), then the CG scalar update
+__global__ void __launch_bounds__(256) k_block_scalars(int mode, int nrhs, int nsite_wg, const int *be_off,
+                                                       const double *partial, double *scal) {
+  __shared__ double sh[256];
+  const int blk = blockIdx.x, r = blockIdx.y;
   const int w0 = be_off[blk] / nsite_wg, w1 = be_off[blk + 1] / nsite_wg;
   double sum = 0;
-  for (int w = w0; w < w1; ++w) sum += partial[(size_t)w * nrhs + r];
-  double *sc = scal + (size_t)i * kScal;
+  for (int w = w0 + (int)threadIdx.x; w < w1; w += 256) sum += partial[(size_t)w * nrhs + r];
+  sh[threadIdx.x] = sum;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  sum = sh[0];
+  double *sc = scal + ((size_t)blk * nrhs + r) * kScal;
   if (mode == 0) {
     sc[1] = (sum > 0.0 && sc[0] > 0.0) ? sc[0] / sum : 0.0;
   } else if (mode == 1) {
@@ -650,8 +717,9 @@ hipError_t block_scatter(int prec, const BlockArgs &b, const Vec &zglob, const V
 
 hipError_t block_scalars(int mode, const BlockArgs &b, const double *partial, double *scal, hipStream_t st) {
   const int n = b.nblocks * b.nrhs;
-  hipLaunchKernelGGL(k_block_scalars, dim3((n + 63) / 64), dim3(64), 0, st, mode, b.nblocks, b.nrhs, b.nsite_wg,
-                     b.be_off, partial, scal);
+  (void)n;
+  hipLaunchKernelGGL(k_block_scalars, dim3(b.nblocks, b.nrhs), dim3(256), 0, st, mode, b.nrhs, b.nsite_wg, b.be_off,
+                     partial, scal);
   return hipGetLastError();
 }
 

@@ -147,9 +147,6 @@ class Field:
                       self.prec, self.nrhs, self.parity)
 
 
-_DT = None
-
-
 def _torch():
     import torch
 
@@ -251,10 +248,10 @@ class Handle:
                                      ctypes.byref(phi_o.c()), _stream(stream)))
 
     # -------------------------------------------------------- solvers
-    def _solve(self, x: Field, b: Field, tol, max_iter, reliable, precond):
+    def _solve(self, x: Field, b: Field, tol, max_iter, reliable, precond, use_graph=1):
         resid = (ctypes.c_double * b.nrhs)()
         st = Stats(0, 0, ctypes.cast(resid, ctypes.POINTER(ctypes.c_double)), 0.0, 0.0)
-        s = Solver(float(tol), int(max_iter), int(reliable), 0)
+        s = Solver(float(tol), int(max_iter), int(reliable), int(use_graph))
         if precond is None:
             rc = lib().cg_solve(self.h, ctypes.byref(x.c()), ctypes.byref(b.c()), ctypes.byref(s), ctypes.byref(st))
         else:
@@ -270,8 +267,8 @@ class Handle:
         return self._solve(x, b, tol, max_iter, reliable, None)
 
     def mspcg_solve(self, x: Field, b: Field, nblk, n_inner, inner_prec=F32, tol=1e-10, max_iter=10000,
-                    reliable=50):
-        return self._solve(x, b, tol, max_iter, reliable, (nblk, n_inner, inner_prec))
+                    reliable=50, use_graph=1):
+        return self._solve(x, b, tol, max_iter, reliable, (nblk, n_inner, inner_prec), use_graph)
 
     # -------------------------------------------------------- debug exports
     def site_maps(self, parity):

@@ -141,3 +141,18 @@ def test_unsupported_blocking(S):
     with pytest.raises(M.MspcgError) as e:
         S.h.local_block_cg(S.h.field(M.F64, 1, 0), S.h.upload(S.rand(1, 95), 0), (2, 1, 1, 1), 2, M.F32)
     assert e.value.status == M.EUNSUPPORTED
+
+
+def test_graph_replay_matches_eager(S):
+    """The captured preconditioner (replayed every outer iteration, with the
+    solver's own eager kernels and host synchronisations between replays) gives
+    bit-identical iterates to eager launches."""
+    nblk = SMALL[2]
+    b = S.rand(2, 96)
+    out = {}
+    for g in (0, 1, 1):
+        fx = S.h.field(M.F64, 2, 0)
+        st = S.h.mspcg_solve(fx, S.h.upload(b, 0), nblk, 3, M.F16, tol=1e-10, use_graph=g)
+        out.setdefault(g, []).append((st["outer_iters"], S.h.download(fx)))
+    assert out[0][0][0] == out[1][0][0] == out[1][1][0]
+    assert np.array_equal(out[0][0][1], out[1][0][1]) and np.array_equal(out[1][0][1], out[1][1][1])
