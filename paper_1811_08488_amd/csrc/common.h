@@ -167,6 +167,106 @@ __device__ inline void store24(bf16 *base, float *norm, size_t site4, int s, int
   }
 }
 
+// A 5D site as loaded (16-byte chunks, plus the norm for F16/BF16), kept
+// raw so that loads can be issued ahead of use and decoded later.
+template <typename S> struct RawSite;
+template <> struct RawSite<double> {
+  double2 c[12];
+  __device__ void load(const double *base, const float *, size_t site4, int s, int Ls) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) c[k] = *reinterpret_cast<const double2 *>(base + chunk_index<double>(site4, s, Ls, k));
+  }
+  template <typename R> __device__ void decode(R v[24]) const {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) { v[2 * k] = (R)c[k].x; v[2 * k + 1] = (R)c[k].y; }
+  }
+};
+template <> struct RawSite<float> {
+  float4 c[6];
+  __device__ void load(const float *base, const float *, size_t site4, int s, int Ls) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) c[k] = *reinterpret_cast<const float4 *>(base + chunk_index<float>(site4, s, Ls, k));
+  }
+  template <typename R> __device__ void decode(R v[24]) const {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      v[4 * k] = (R)c[k].x; v[4 * k + 1] = (R)c[k].y; v[4 * k + 2] = (R)c[k].z; v[4 * k + 3] = (R)c[k].w;
+    }
+  }
+};
+template <> struct RawSite<_Float16> {
+  uint4 c[3];
+  float n;
+  __device__ void load(const _Float16 *base, const float *norm, size_t site4, int s, int Ls) {
+    n = norm[site4 * Ls + s];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c[k] = *reinterpret_cast<const uint4 *>(base + chunk_index<_Float16>(site4, s, Ls, k));
+  }
+  template <typename R> __device__ void decode(R v[24]) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const uint32_t w[4] = {c[k].x, c[k].y, c[k].z, c[k].w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        union { uint32_t u; _Float16 h[2]; } t;
+        t.u = w[j];
+        v[8 * k + 2 * j] = (R)((float)t.h[0] * n);
+        v[8 * k + 2 * j + 1] = (R)((float)t.h[1] * n);
+      }
+    }
+  }
+};
+template <> struct RawSite<bf16> {
+  uint4 c[3];
+  float n;
+  __device__ void load(const bf16 *base, const float *norm, size_t site4, int s, int Ls) {
+    n = norm[site4 * Ls + s];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c[k] = *reinterpret_cast<const uint4 *>(base + chunk_index<bf16>(site4, s, Ls, k));
+  }
+  template <typename R> __device__ void decode(R v[24]) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const uint32_t w[4] = {c[k].x, c[k].y, c[k].z, c[k].w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        v[8 * k + 2 * j] = (R)(bf16_to_float((uint16_t)(w[j] & 0xffffu)) * n);
+        v[8 * k + 2 * j + 1] = (R)(bf16_to_float((uint16_t)(w[j] >> 16)) * n);
+      }
+    }
+  }
+};
+
+// 16 bytes of link data (2 doubles, 4 floats or 8 halves) widened to the compute type.
+template <typename R> __device__ inline void widen16(const double *p, R *o) {
+  const double2 t = *reinterpret_cast<const double2 *>(p);
+  o[0] = (R)t.x; o[1] = (R)t.y;
+}
+template <typename R> __device__ inline void widen16(const float *p, R *o) {
+  const float4 t = *reinterpret_cast<const float4 *>(p);
+  o[0] = (R)t.x; o[1] = (R)t.y; o[2] = (R)t.z; o[3] = (R)t.w;
+}
+template <typename R> __device__ inline void widen16(const _Float16 *p, R *o) {
+  const uint4 t = *reinterpret_cast<const uint4 *>(p);
+  const uint32_t w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    union { uint32_t u; _Float16 h[2]; } c;
+    c.u = w[j];
+    o[2 * j] = (R)(float)c.h[0];
+    o[2 * j + 1] = (R)(float)c.h[1];
+  }
+}
+template <typename R> __device__ inline void widen16(const bf16 *p, R *o) {
+  const uint4 t = *reinterpret_cast<const uint4 *>(p);
+  const uint32_t w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    o[2 * j] = (R)bf16_to_float((uint16_t)(w[j] & 0xffffu));
+    o[2 * j + 1] = (R)bf16_to_float((uint16_t)(w[j] >> 16));
+  }
+}
+
 // ---------------------------------------------------------------- links
 // One 3x3 complex matrix = 18 reals [row][col][re,im]; stored in the
 // spinor storage type without a scale (|U_ij| <= 1).
@@ -245,20 +345,26 @@ __device__ inline void project(const R v[24], R h[12]) {
   }
 }
 
-// w = U h for both spins (U already includes the dagger of backward links)
+// w = U h for both spins (U already includes the dagger of backward links),
+// written as chains of fused multiply-adds (4 per complex multiply-add).
 template <typename R>
 __device__ inline void link_mul(const R u[18], const R h[12], R w[12]) {
 #pragma unroll
   for (int k = 0; k < 2; ++k)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      R re = 0, im = 0;
+      const R *ua = u + a * 6;
+      const R *hk = h + k * 6;
+      R re = ua[0] * hk[0];
+      R im = ua[0] * hk[1];
+      re = fma(-ua[1], hk[1], re);
+      im = fma(ua[1], hk[0], im);
 #pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const R ur = u[(a * 3 + b) * 2], ui = u[(a * 3 + b) * 2 + 1];
-        const R hr = h[(k * 3 + b) * 2], hi = h[(k * 3 + b) * 2 + 1];
-        re += ur * hr - ui * hi;
-        im += ur * hi + ui * hr;
+      for (int b = 1; b < 3; ++b) {
+        re = fma(ua[2 * b], hk[2 * b], re);
+        re = fma(-ua[2 * b + 1], hk[2 * b + 1], re);
+        im = fma(ua[2 * b], hk[2 * b + 1], im);
+        im = fma(ua[2 * b + 1], hk[2 * b], im);
       }
       w[(k * 3 + a) * 2] = re;
       w[(k * 3 + a) * 2 + 1] = im;

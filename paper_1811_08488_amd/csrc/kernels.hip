@@ -22,28 +22,71 @@ __device__ inline void zero24(R v[24]) {
   for (int k = 0; k < 24; ++k) v[k] = 0;
 }
 
-// v <- a v + b P_chi v (dag = 0) or a v + b P_chi^+ v (dag = 1) on the Ls column
+// ---------------------------------------------------------------- fifth-dimension exchange
+// The Ls values of one (4D site, rhs) sit on Ls consecutive lanes.  Coupling
+// s to s-1 / s+1 is a cyclic rotation inside that group of lanes:
+//  * Ls == 16: the group is one DPP row; row_ror moves the value in the same
+//    VALU instruction stream, with no LDS traffic and no barrier;
+//  * Ls divides 64: groups never straddle a wavefront; ds_bpermute;
+//  * otherwise (Ls = 12, 24, ...): through LDS with workgroup barriers.
+__device__ inline int rot_prev_dpp(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x121, 0xF, 0xF, false); }
+__device__ inline int rot_next_dpp(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x12F, 0xF, 0xF, false); }
+__device__ inline float rot_prev_dpp(float x) { return __builtin_bit_cast(float, rot_prev_dpp(__builtin_bit_cast(int, x))); }
+__device__ inline float rot_next_dpp(float x) { return __builtin_bit_cast(float, rot_next_dpp(__builtin_bit_cast(int, x))); }
+__device__ inline double rot_prev_dpp(double x) {
+  const int2 t = __builtin_bit_cast(int2, x);
+  return __builtin_bit_cast(double, make_int2(rot_prev_dpp(t.x), rot_prev_dpp(t.y)));
+}
+__device__ inline double rot_next_dpp(double x) {
+  const int2 t = __builtin_bit_cast(int2, x);
+  return __builtin_bit_cast(double, make_int2(rot_next_dpp(t.x), rot_next_dpp(t.y)));
+}
+__device__ inline float perm(int addr, float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, x)));
+}
+__device__ inline double perm(int addr, double x) {
+  const int2 t = __builtin_bit_cast(int2, x);
+  return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_ds_bpermute(addr, t.x), __builtin_amdgcn_ds_bpermute(addr, t.y)));
+}
+
+// v <- a v + b P_chi v (DAG = 0) or a v + b P_chi^+ v (DAG = 1) on the Ls column
 // held one s per lane.  P_chi = P- S+ + P+ S-: chirality + (reals 0..11) takes
-// s-1, chirality - (reals 12..23) takes s+1, with the -mf corner.  LDS is
-// structure-of-arrays [24][nthr] so lane-consecutive accesses are conflict free.
-template <typename R>
-__device__ inline void pchi_comb(R *lds, int nthr, int tid, int s, int Ls, R a, R b, R mf, int dag, R v[24]) {
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < 24; ++k) lds[k * nthr + tid] = v[k];
-  __syncthreads();
-  const int tm = (s > 0) ? tid - 1 : tid + Ls - 1;
-  const int tp = (s < Ls - 1) ? tid + 1 : tid - (Ls - 1);
+// s-1, chirality - (reals 12..23) takes s+1, with the -mf corner; the adjoint
+// swaps the directions.  Must be reached by all threads of the workgroup.
+template <int DAG, typename R>
+__device__ inline void pchi_comb(R *lds, int nthr, int tid, int s, int Ls, R a, R b, R mf, R v[24]) {
   const R cm = (s > 0) ? R(1) : -mf;
   const R cp = (s < Ls - 1) ? R(1) : -mf;
-  const int tu = dag ? tp : tm;
-  const int tl = dag ? tm : tp;
-  const R cu = b * (dag ? cp : cm);
-  const R cl = b * (dag ? cm : cp);
+  const R cu = b * (DAG ? cp : cm);
+  const R cl = b * (DAG ? cm : cp);
+  if (Ls == 16) {
 #pragma unroll
-  for (int k = 0; k < 12; ++k) v[k] = a * v[k] + cu * lds[k * nthr + tu];
+    for (int k = 0; k < 12; ++k) v[k] = a * v[k] + cu * (DAG ? rot_next_dpp(v[k]) : rot_prev_dpp(v[k]));
 #pragma unroll
-  for (int k = 12; k < 24; ++k) v[k] = a * v[k] + cl * lds[k * nthr + tl];
+    for (int k = 12; k < 24; ++k) v[k] = a * v[k] + cl * (DAG ? rot_prev_dpp(v[k]) : rot_next_dpp(v[k]));
+  } else if ((64 % Ls) == 0) {
+    const int lane = tid & 63;
+    const int am = 4 * ((s > 0) ? lane - 1 : lane + Ls - 1);
+    const int ap = 4 * ((s < Ls - 1) ? lane + 1 : lane - (Ls - 1));
+    const int au = DAG ? ap : am, al = DAG ? am : ap;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = a * v[k] + cu * perm(au, v[k]);
+#pragma unroll
+    for (int k = 12; k < 24; ++k) v[k] = a * v[k] + cl * perm(al, v[k]);
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 24; ++k) lds[k * nthr + tid] = v[k];
+    __syncthreads();
+    const int tm = (s > 0) ? tid - 1 : tid + Ls - 1;
+    const int tp = (s < Ls - 1) ? tid + 1 : tid - (Ls - 1);
+    const int tu = DAG ? tp : tm;
+    const int tl = DAG ? tm : tp;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = a * v[k] + cu * lds[k * nthr + tu];
+#pragma unroll
+    for (int k = 12; k < 24; ++k) v[k] = a * v[k] + cl * lds[k * nthr + tl];
+  }
 }
 
 // ---------------------------------------------------------------- dense fifth-dimension matrices
@@ -171,67 +214,97 @@ __device__ inline void wg_partial(double *ldsd, int nthr, int tid, int Ls, int n
 // indexed by cb.  Otherwise (block domains) they are indexed by the position
 // in the list, and neighbours outside the domain point at the input list's
 // zero site, which is never written.
+template <int MU, int PLUS, typename R>
+__device__ inline void hop_term(const R v[24], const R u[18], R acc[24]) {
+  R h[12], w[12];
+  project<MU, PLUS ? 1 : -1>(v, h);
+  link_mul(u, h, w);
+  accumulate<MU, PLUS ? 1 : -1>(acc, w);
+}
+
 template <typename S, int DAG, int PRE, int EPI, int DOT, int GLOBAL>
 __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
   using R = typename Traits<S>::R;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int Ls = a.Ls, nrhs = a.nrhs;
+  const int Ls = a.Ls, nrhs = a.nrhs, nsw = a.nsite_wg;
   const int s = threadIdx.x, r = threadIdx.y, sl = threadIdx.z;
-  const int nthr = Ls * nrhs * a.nsite_wg;
+  const int nthr = Ls * nrhs * nsw;
   const int tid = s + Ls * (r + nrhs * sl);
-  R *lds = reinterpret_cast<R *>(smem);
-  R *Xl = lds + 24 * nthr;
+  R *lds = reinterpret_cast<R *>(smem);  // [24][nthr] fifth-dimension exchanges
+  R *Lk = lds + 24 * nthr;               // [nsite_wg][8][18] links of this workgroup's sites
+  R *Xl = Lk + nsw * 144;                // [2][Ls][Ls] dense epilogue matrix
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int site = tile * a.nsite_wg + sl;
+  const int site = tile * nsw + sl;
   const int cbr = (site < a.nsites) ? a.site_cb[site] : -1;
   const bool active = cbr >= 0;
   const int cb = active ? cbr : 0;
   const int self = GLOBAL ? cb : site;  // index of this site in tables and outputs
 
+  // the first neighbour spinor is requested before anything waits
+  const int *nb = a.nbr + (size_t)(active ? self : 0) * 8;
+  const S *in = reinterpret_cast<const S *>(a.in);
+  const size_t rin = (size_t)r * a.in_stride;
+  RawSite<S> cur, nxt;
+  cur.load(in, a.in_norm, rin + (active ? nb[0] : a.zero_site), s, Ls);
+
+  // the links of all sites of the workgroup, staged once into LDS with
+  // 16-byte loads (every link is used by all Ls x nrhs lanes of its site)
+  {
+    const S *links = reinterpret_cast<const S *>(a.links);
+    constexpr int per = 16 / sizeof(S);
+    constexpr int nchunk = 144 / per;
+    for (int i = tid; i < nsw * nchunk; i += nthr) {
+      const int q = i / nchunk, c = i - q * nchunk;
+      const int st = tile * nsw + q;
+      const int cq = st < a.nsites ? max(a.site_cb[st], 0) : 0;
+      widen16<R>(links + (size_t)cq * 144 + c * per, Lk + q * 144 + c * per);
+    }
+  }
   if (EPI == EPI_DENSE) {
     const R *Xg = reinterpret_cast<const R *>(a.mat);
     for (int i = tid; i < 2 * Ls * Ls; i += nthr) Xl[i] = Xg[i];
   }
+  __syncthreads();
 
-  const S *in = reinterpret_cast<const S *>(a.in);
-  const S *links = reinterpret_cast<const S *>(a.links);
-  const int *nb = a.nbr + (size_t)(active ? self : 0) * 8;
-  const size_t rin = (size_t)r * a.in_stride;
   R acc[24];
   zero24(acc);
-
-  // kept rolled: unrolling lets the compiler hoist all eight directions'
-  // loads, which exhausts the register file
+  const R *Lsite = Lk + sl * 144;
+  // One direction is always in flight ahead of the one being computed: the
+  // forward neighbour of mu uses buffer `cur`, the backward one `nxt`.  The
+  // loop over mu stays rolled on purpose (unrolled, the compiler hoists all
+  // eight directions' loads and runs out of registers).
+  // FP64 spinors are large: there the register budget is spent on occupancy
+  // instead of the prefetch (each direction loads just before it is used).
+  constexpr bool kPrefetch = sizeof(R) != 8;
 #pragma unroll 1
-  for (int d = 0; d < 8; ++d) {
-    const int j = active ? nb[d] : a.zero_site;
-    R v[24], u[18], h[12], w[12];
-    load24<R>(in, a.in_norm, rin + j, s, Ls, v);
-    load18<R>(links, (size_t)cb * 8 + d, u);
-    if (PRE) pchi_comb<R>(lds, nthr, tid, s, Ls, (R)a.mphi_b, (R)a.mphi_c, (R)a.mf, 0, v);
-    const int mu = d >> 1;
-    // SGN = +1 selects (1 - g_mu): forward for H, backward for H^+
-    const bool plus = ((d & 1) != 0) == (DAG != 0);
-    if (mu == 0) {
-      if (plus) { project<0, 1>(v, h); link_mul(u, h, w); accumulate<0, 1>(acc, w); }
-      else      { project<0, -1>(v, h); link_mul(u, h, w); accumulate<0, -1>(acc, w); }
-    } else if (mu == 1) {
-      if (plus) { project<1, 1>(v, h); link_mul(u, h, w); accumulate<1, 1>(acc, w); }
-      else      { project<1, -1>(v, h); link_mul(u, h, w); accumulate<1, -1>(acc, w); }
-    } else if (mu == 2) {
-      if (plus) { project<2, 1>(v, h); link_mul(u, h, w); accumulate<2, 1>(acc, w); }
-      else      { project<2, -1>(v, h); link_mul(u, h, w); accumulate<2, -1>(acc, w); }
-    } else {
-      if (plus) { project<3, 1>(v, h); link_mul(u, h, w); accumulate<3, 1>(acc, w); }
-      else      { project<3, -1>(v, h); link_mul(u, h, w); accumulate<3, -1>(acc, w); }
+  for (int mu = 0; mu < 4; ++mu) {
+    if (kPrefetch) nxt.load(in, a.in_norm, rin + (active ? nb[2 * mu + 1] : a.zero_site), s, Ls);
+#pragma unroll
+    for (int bw = 0; bw < 2; ++bw) {
+      const int d = 2 * mu + bw;
+      if (kPrefetch && bw == 1 && mu < 3) cur.load(in, a.in_norm, rin + (active ? nb[d + 1] : a.zero_site), s, Ls);
+      if (!kPrefetch && d > 0) cur.load(in, a.in_norm, rin + (active ? nb[d] : a.zero_site), s, Ls);
+      R v[24], u[18];
+      if (bw == 0 || !kPrefetch) cur.decode(v); else nxt.decode(v);
+      if (PRE) pchi_comb<0, R>(lds, nthr, tid, s, Ls, (R)a.mphi_b, (R)a.mphi_c, (R)a.mf, v);
+#pragma unroll
+      for (int k = 0; k < 18; ++k) u[k] = Lsite[d * 18 + k];
+      // (1 - g_mu) for the forward hop of H and the backward hop of H^+
+      const bool plus = (bw != 0) == (DAG != 0);
+      switch (mu) {
+        case 0: if (plus) hop_term<0, 1>(v, u, acc); else hop_term<0, 0>(v, u, acc); break;
+        case 1: if (plus) hop_term<1, 1>(v, u, acc); else hop_term<1, 0>(v, u, acc); break;
+        case 2: if (plus) hop_term<2, 1>(v, u, acc); else hop_term<2, 0>(v, u, acc); break;
+        default: if (plus) hop_term<3, 1>(v, u, acc); else hop_term<3, 0>(v, u, acc); break;
+      }
     }
   }
 
   const R scale = (R)a.scale;
   if (EPI == EPI_DENSE) {
-    dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * a.nsite_wg, scale, acc);
+    dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * nsw, scale, acc);
   } else if (EPI == EPI_MPHIDAG || EPI == EPI_M5DAG_MPHIDAG) {
-    pchi_comb<R>(lds, nthr, tid, s, Ls, (R)a.mphi_b, (R)a.mphi_c, (R)a.mf, 1, acc);
+    pchi_comb<1, R>(lds, nthr, tid, s, Ls, (R)a.mphi_b, (R)a.mphi_c, (R)a.mf, acc);
 #pragma unroll
     for (int k = 0; k < 24; ++k) acc[k] *= scale;
   } else {
@@ -243,7 +316,7 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     R o[24];
     load24<R>(reinterpret_cast<const S *>(a.other), a.other_norm, (size_t)r * a.other_stride + oi, s, Ls, o);
     // M_5 = alpha - beta P_chi ; M_5^+ = alpha - beta P_chi^+
-    pchi_comb<R>(lds, nthr, tid, s, Ls, (R)a.m5_alpha, (R)(-a.m5_beta), (R)a.mf, EPI == EPI_M5DAG_MPHIDAG, o);
+    pchi_comb<EPI == EPI_M5DAG_MPHIDAG ? 1 : 0, R>(lds, nthr, tid, s, Ls, (R)a.m5_alpha, (R)(-a.m5_beta), (R)a.mf, o);
 #pragma unroll
     for (int k = 0; k < 24; ++k) acc[k] += o[k];
   }
@@ -260,14 +333,14 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
       for (int k = 0; k < 24; ++k) t += w[k] * acc[k];
       val = (double)t;
     }
-    wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, nrhs, a.nsite_wg, val, a.partial, tile);
+    wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, nrhs, nsw, val, a.partial, tile);
   }
 }
 
 template <typename S>
 static size_t hop_lds_bytes(const HopArgs &a, int nthr, int epi, int dot) {
   using R = typename Traits<S>::R;
-  size_t b = (size_t)24 * nthr * sizeof(R);
+  size_t b = ((size_t)24 * nthr + (size_t)144 * a.nsite_wg) * sizeof(R);
   if (epi == EPI_DENSE) b += (size_t)2 * a.Ls * a.Ls * sizeof(R);
   if (dot) b = std::max(b, (size_t)2 * nthr * sizeof(double));
   return b;
@@ -337,8 +410,10 @@ __global__ void __launch_bounds__(256) op5_kernel(const Op5Args a) {
   load24<R>(reinterpret_cast<const S *>(a.in), a.in_norm, idx, s, Ls, v);
   if (a.dense)
     dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * a.nsite_wg, R(1), v);
+  else if (a.dag)
+    pchi_comb<1, R>(lds, nthr, tid, s, Ls, (R)a.a, (R)a.b, (R)a.mf, v);
   else
-    pchi_comb<R>(lds, nthr, tid, s, Ls, (R)a.a, (R)a.b, (R)a.mf, a.dag, v);
+    pchi_comb<0, R>(lds, nthr, tid, s, Ls, (R)a.a, (R)a.b, (R)a.mf, v);
   if (active) store24<R>(reinterpret_cast<S *>(a.out), a.out_norm, idx, s, Ls, v);
 }
 
