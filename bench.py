@@ -70,7 +70,8 @@ def build_problem(w, torch):
 
 
 def time_dslash(h, A, w, prec, reps=50, warm=5):
-    """Median duration of one dslash_eo launch (HIP events on the launch stream)."""
+    """Average duration of one dslash_eo launch: HIP events on the stream the
+    kernel is launched on, bracketing `reps` back-to-back launches."""
     import torch
 
     stream = torch.cuda.Stream()
@@ -81,18 +82,47 @@ def time_dslash(h, A, w, prec, reps=50, warm=5):
         h.convert(fin, src, stream=stream)
         for _ in range(warm):
             h.dslash_eo(fout, fin, 0, stream=stream)
-        times = []
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
         for _ in range(reps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
             h.dslash_eo(fout, fin, 0, stream=stream)
-            e1.record(stream)
-            times.append((e0, e1))
+        e1.record(stream)
         stream.synchronize()
-    ms = float(np.median([a.elapsed_time(b) for a, b in times]))
+    ms = e0.elapsed_time(e1) / reps
     nsites5 = (A.V // 2) * w.Ls * w.nrhs
     bytes_ = dslash_bytes_per_site(prec, w.Ls, w.nrhs) * nsites5
     return {"ms": ms, "bytes": bytes_, "gbs": bytes_ / (ms * 1e-3) / 1e9}
+
+
+def kernel_source_hash():
+    """SHA-256 of the HIP sources the hop kernel is compiled from."""
+    import hashlib
+
+    hsh = hashlib.sha256()
+    for f in ("kernels.hip", "common.h", "internal.h"):
+        with open(os.path.join(ROOT, "paper_1811_08488_amd", "csrc", f), "rb") as fh:
+            hsh.update(fh.read())
+    return hsh.hexdigest()
+
+
+def measured_traffic(workload, prec_name):
+    """HBM bytes per dslash_eo launch from the committed hardware-counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or
+    None when there is none for this workload or the kernel source changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"hop_kernel_dslash_eo_{workload}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    v = kv.get(f"traffic_bytes_per_launch_{prec_name}")
+    return None if v is None else float(v)
 
 
 def cpu_baseline(w, U, outer_iters, n_inner, nblk, budget_s=20.0):
@@ -237,7 +267,9 @@ def main():
         "dslash_eo": {p: {"us": d["ms"] * 1e3, "GB/s": d["gbs"], "frac_hbm": d["gbs"] / HBM_PEAK_GBS}
                       for p, d in dsl.items()},
         "roofline": {"bound": "hbm", "achieved": main_k["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": main_k["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": "hop_kernel f64 (dslash_eo)"},
+                     "frac": main_k["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(w.name, "f64"),
+                     "algorithmic_bytes": main_k["bytes"], "avg_launch_us": main_k["ms"] * 1e3,
+                     "kernel": "hop_kernel<double> (dslash_eo, FP64)"},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, U, stats[-1]["outer_iters"], k, nblk)

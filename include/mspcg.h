@@ -80,7 +80,7 @@ typedef struct {
   int Ls;       /* fifth dimension, 2 <= Ls <= MSPCG_MAX_LS */
   double M5;    /* domain-wall height */
   double mf;    /* quark mass */
-  double b, c;  /* Moebius coefficients (Shamir: b = 1, c = 0) */
+  double b, c;  /* Moebius coefficients (Shamir: b = 1, c = 0); b != 0 */
   int t_bc;     /* -1 antiperiodic, +1 periodic in time */
 } mspcg_dwf;
 
@@ -117,7 +117,9 @@ typedef struct mspcg_handle mspcg_handle;
 
 /* Create a handle for one lattice/action on the current HIP device.  The
  * gauge field (device, FP64, physical links) is copied and repacked on
- * `stream`; the caller may free it after the call returns. */
+ * `stream`; the caller may free it after the call returns.
+ * MSPCG_EUNSUPPORTED for b = 0 (the hop kernels factor b out of
+ * M_phi = b + c P_chi). */
 mspcg_status mspcg_create(mspcg_handle **h, const mspcg_dwf *p, const double *gauge_dev_f64, void *stream);
 mspcg_status mspcg_destroy(mspcg_handle *h);
 

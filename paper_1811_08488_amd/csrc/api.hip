@@ -890,6 +890,7 @@ mspcg_status mspcg_create(mspcg_handle **hp, const mspcg_dwf *p, const double *g
     const int Ls = p->Ls;
     const double q = h->beta5 / h->alpha5;
     if (std::abs(1 + p->mf * std::pow(q, Ls)) < 1e-300 || h->alpha5 == 0.0) fail(MSPCG_EINVAL, "M_5 is singular");
+    if (p->b == 0.0) fail(MSPCG_EUNSUPPORTED, "Moebius b = 0 is not supported");
     hipStream_t st = h->stream;
     // index maps
     const int *L = p->L;

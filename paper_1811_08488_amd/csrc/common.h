@@ -317,32 +317,41 @@ __device__ inline void load18(const bf16 *base, size_t m, R u[18]) {
 // and B_t = 1.  For SGN = +1 the projector is (1 - g_mu), for SGN = -1 it is
 // (1 + g_mu).  (1 - SGN g_mu) psi has upper half h = u - SGN B l and lower half
 // -SGN B^+ h, so only h (2 spins x 3 colours) is multiplied by the link.
+// h = X + Y with X = u (the upper spins) and Y = -SGN B l.
 // Indexing: v[(spin*3 + colour)*2 + ri], h[(k*3 + colour)*2 + ri], k = 0,1.
 template <int MU, int SGN, typename R>
-__device__ inline void project(const R v[24], R h[12]) {
+__device__ inline void project_parts(const R v[24], R X[12], R Y[12]) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const R u0r = v[(0 * 3 + c) * 2], u0i = v[(0 * 3 + c) * 2 + 1];
-    const R u1r = v[(1 * 3 + c) * 2], u1i = v[(1 * 3 + c) * 2 + 1];
     const R l0r = v[(2 * 3 + c) * 2], l0i = v[(2 * 3 + c) * 2 + 1];
     const R l1r = v[(3 * 3 + c) * 2], l1i = v[(3 * 3 + c) * 2 + 1];
-    R h0r, h0i, h1r, h1i;
+    R y0r, y0i, y1r, y1i;  // -SGN B l
     if (MU == 0) {  // B l = (-i l1, -i l0)
-      h0r = u0r - SGN * l1i; h0i = u0i + SGN * l1r;
-      h1r = u1r - SGN * l0i; h1i = u1i + SGN * l0r;
+      y0r = -SGN * l1i; y0i = SGN * l1r;
+      y1r = -SGN * l0i; y1i = SGN * l0r;
     } else if (MU == 1) {  // B l = (-l1, l0)
-      h0r = u0r + SGN * l1r; h0i = u0i + SGN * l1i;
-      h1r = u1r - SGN * l0r; h1i = u1i - SGN * l0i;
+      y0r = SGN * l1r; y0i = SGN * l1i;
+      y1r = -SGN * l0r; y1i = -SGN * l0i;
     } else if (MU == 2) {  // B l = (-i l0, i l1)
-      h0r = u0r - SGN * l0i; h0i = u0i + SGN * l0r;
-      h1r = u1r + SGN * l1i; h1i = u1i - SGN * l1r;
+      y0r = -SGN * l0i; y0i = SGN * l0r;
+      y1r = SGN * l1i; y1i = -SGN * l1r;
     } else {  // B l = l
-      h0r = u0r - SGN * l0r; h0i = u0i - SGN * l0i;
-      h1r = u1r - SGN * l1r; h1i = u1i - SGN * l1i;
+      y0r = -SGN * l0r; y0i = -SGN * l0i;
+      y1r = -SGN * l1r; y1i = -SGN * l1i;
     }
-    h[(0 * 3 + c) * 2] = h0r; h[(0 * 3 + c) * 2 + 1] = h0i;
-    h[(1 * 3 + c) * 2] = h1r; h[(1 * 3 + c) * 2 + 1] = h1i;
+    X[(0 * 3 + c) * 2] = v[(0 * 3 + c) * 2]; X[(0 * 3 + c) * 2 + 1] = v[(0 * 3 + c) * 2 + 1];
+    X[(1 * 3 + c) * 2] = v[(1 * 3 + c) * 2]; X[(1 * 3 + c) * 2 + 1] = v[(1 * 3 + c) * 2 + 1];
+    Y[(0 * 3 + c) * 2] = y0r; Y[(0 * 3 + c) * 2 + 1] = y0i;
+    Y[(1 * 3 + c) * 2] = y1r; Y[(1 * 3 + c) * 2 + 1] = y1i;
   }
+}
+
+template <int MU, int SGN, typename R>
+__device__ inline void project(const R v[24], R h[12]) {
+  R X[12], Y[12];
+  project_parts<MU, SGN>(v, X, Y);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) h[k] = X[k] + Y[k];
 }
 
 // w = U h for both spins (U already includes the dagger of backward links),
@@ -371,32 +380,69 @@ __device__ inline void link_mul(const R u[18], const R h[12], R w[12]) {
     }
 }
 
-// acc += (w, -SGN B^+ w): B_x^+ w = (i w1, i w0), B_y^+ w = (w1, -w0),
-// B_z^+ w = (i w0, -i w1), B_t^+ w = (w0, w1).
+// acc += (w, -SGN B^+ w) for one colour c: B_x^+ w = (i w1, i w0),
+// B_y^+ w = (w1, -w0), B_z^+ w = (i w0, -i w1), B_t^+ w = (w0, w1).
+template <int MU, int SGN, typename R>
+__device__ inline void accumulate_colour(R acc[24], int c, R w0r, R w0i, R w1r, R w1i) {
+  acc[(0 * 3 + c) * 2] += w0r; acc[(0 * 3 + c) * 2 + 1] += w0i;
+  acc[(1 * 3 + c) * 2] += w1r; acc[(1 * 3 + c) * 2 + 1] += w1i;
+  R l0r, l0i, l1r, l1i;  // -SGN B^+ w
+  if (MU == 0) {
+    l0r = SGN * w1i; l0i = -SGN * w1r;
+    l1r = SGN * w0i; l1i = -SGN * w0r;
+  } else if (MU == 1) {
+    l0r = -SGN * w1r; l0i = -SGN * w1i;
+    l1r = SGN * w0r; l1i = SGN * w0i;
+  } else if (MU == 2) {
+    l0r = SGN * w0i; l0i = -SGN * w0r;
+    l1r = -SGN * w1i; l1i = SGN * w1r;
+  } else {
+    l0r = -SGN * w0r; l0i = -SGN * w0i;
+    l1r = -SGN * w1r; l1i = -SGN * w1i;
+  }
+  acc[(2 * 3 + c) * 2] += l0r; acc[(2 * 3 + c) * 2 + 1] += l0i;
+  acc[(3 * 3 + c) * 2] += l1r; acc[(3 * 3 + c) * 2 + 1] += l1i;
+}
+
 template <int MU, int SGN, typename R>
 __device__ inline void accumulate(R acc[24], const R w[12]) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const R w0r = w[(0 * 3 + c) * 2], w0i = w[(0 * 3 + c) * 2 + 1];
-    const R w1r = w[(1 * 3 + c) * 2], w1i = w[(1 * 3 + c) * 2 + 1];
-    acc[(0 * 3 + c) * 2] += w0r; acc[(0 * 3 + c) * 2 + 1] += w0i;
-    acc[(1 * 3 + c) * 2] += w1r; acc[(1 * 3 + c) * 2 + 1] += w1i;
-    R l0r, l0i, l1r, l1i;  // -SGN B^+ w
-    if (MU == 0) {
-      l0r = SGN * w1i; l0i = -SGN * w1r;
-      l1r = SGN * w0i; l1i = -SGN * w0r;
-    } else if (MU == 1) {
-      l0r = -SGN * w1r; l0i = -SGN * w1i;
-      l1r = SGN * w0r; l1i = SGN * w0i;
-    } else if (MU == 2) {
-      l0r = SGN * w0i; l0i = -SGN * w0r;
-      l1r = -SGN * w1i; l1i = SGN * w1r;
-    } else {
-      l0r = -SGN * w0r; l0i = -SGN * w0i;
-      l1r = -SGN * w1r; l1i = -SGN * w1i;
+  for (int c = 0; c < 3; ++c)
+    accumulate_colour<MU, SGN>(acc, c, w[(0 * 3 + c) * 2], w[(0 * 3 + c) * 2 + 1], w[(1 * 3 + c) * 2],
+                               w[(1 * 3 + c) * 2 + 1]);
+}
+
+// One direction of the hop for one 5D site, given the projected neighbour
+// half spinor h: multiply h by the link U (18 reals, row-major) one colour
+// row at a time and add each row's result to both halves of the accumulator
+// straight away, so that only the accumulator, the half spinor and one link
+// row are live.
+template <int MU, int SGN, typename R>
+__device__ inline void hop_half(const R h[12], const R *U, R acc[24]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    R ur[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ur[k] = U[6 * a + k];
+    R w[4];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const R *hk = h + 6 * k;
+      R re = ur[0] * hk[0];
+      R im = ur[0] * hk[1];
+      re = fma(-ur[1], hk[1], re);
+      im = fma(ur[1], hk[0], im);
+#pragma unroll
+      for (int b = 1; b < 3; ++b) {
+        re = fma(ur[2 * b], hk[2 * b], re);
+        re = fma(-ur[2 * b + 1], hk[2 * b + 1], re);
+        im = fma(ur[2 * b], hk[2 * b + 1], im);
+        im = fma(ur[2 * b + 1], hk[2 * b], im);
+      }
+      w[2 * k] = re;
+      w[2 * k + 1] = im;
     }
-    acc[(2 * 3 + c) * 2] += l0r; acc[(2 * 3 + c) * 2 + 1] += l0i;
-    acc[(3 * 3 + c) * 2] += l1r; acc[(3 * 3 + c) * 2 + 1] += l1i;
+    accumulate_colour<MU, SGN>(acc, a, w[0], w[1], w[2], w[3]);
   }
 }
 

@@ -49,22 +49,26 @@ __device__ inline double perm(int addr, double x) {
   return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_ds_bpermute(addr, t.x), __builtin_amdgcn_ds_bpermute(addr, t.y)));
 }
 
+// Exchange modes, fixed per launch from Ls (the kernels are instantiated per mode).
+constexpr int kXDpp16 = 0, kXPerm = 1, kXLds = 2;
+static inline int xmode(int Ls) { return Ls == 16 ? kXDpp16 : (64 % Ls == 0 ? kXPerm : kXLds); }
+
 // v <- a v + b P_chi v (DAG = 0) or a v + b P_chi^+ v (DAG = 1) on the Ls column
 // held one s per lane.  P_chi = P- S+ + P+ S-: chirality + (reals 0..11) takes
 // s-1, chirality - (reals 12..23) takes s+1, with the -mf corner; the adjoint
 // swaps the directions.  Must be reached by all threads of the workgroup.
-template <int DAG, typename R>
+template <int DAG, int XM, typename R>
 __device__ inline void pchi_comb(R *lds, int nthr, int tid, int s, int Ls, R a, R b, R mf, R v[24]) {
   const R cm = (s > 0) ? R(1) : -mf;
   const R cp = (s < Ls - 1) ? R(1) : -mf;
   const R cu = b * (DAG ? cp : cm);
   const R cl = b * (DAG ? cm : cp);
-  if (Ls == 16) {
+  if (XM == kXDpp16) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) v[k] = a * v[k] + cu * (DAG ? rot_next_dpp(v[k]) : rot_prev_dpp(v[k]));
 #pragma unroll
     for (int k = 12; k < 24; ++k) v[k] = a * v[k] + cl * (DAG ? rot_prev_dpp(v[k]) : rot_next_dpp(v[k]));
-  } else if ((64 % Ls) == 0) {
+  } else if (XM == kXPerm) {
     const int lane = tid & 63;
     const int am = 4 * ((s > 0) ? lane - 1 : lane + Ls - 1);
     const int ap = 4 * ((s < Ls - 1) ? lane + 1 : lane - (Ls - 1));
@@ -87,6 +91,51 @@ __device__ inline void pchi_comb(R *lds, int nthr, int tid, int s, int Ls, R a, 
 #pragma unroll
     for (int k = 12; k < 24; ++k) v[k] = a * v[k] + cl * lds[k * nthr + tl];
   }
+}
+
+// Projected half spinor of (1 + pc P_chi) v for the hop in direction MU:
+// h(s) = X(s) + Y(s) + cu X(s-1) + cl Y(s+1) with X, Y the two parts of the
+// projection (P_chi takes the upper spins from s-1 and the lower ones from
+// s+1, with the -mf corners folded into cu, cl).  Projecting before the
+// exchange moves 12 + 12 reals instead of 24 and needs no full M_phi v.
+// Must be reached by all threads of the workgroup.
+template <int MU, int SGN, int XM, typename R>
+__device__ inline void project_pre(R *lds, int nthr, int tid, int s, int Ls, R cu, R cl, const R v[24], R h[12]) {
+  R X[12], Y[12];
+  project_parts<MU, SGN>(v, X, Y);
+  if (XM == kXDpp16) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) h[k] = X[k] + Y[k] + cu * rot_prev_dpp(X[k]) + cl * rot_next_dpp(Y[k]);
+  } else if (XM == kXPerm) {
+    const int lane = tid & 63;
+    const int am = 4 * ((s > 0) ? lane - 1 : lane + Ls - 1);
+    const int ap = 4 * ((s < Ls - 1) ? lane + 1 : lane - (Ls - 1));
+#pragma unroll
+    for (int k = 0; k < 12; ++k) h[k] = X[k] + Y[k] + cu * perm(am, X[k]) + cl * perm(ap, Y[k]);
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      lds[k * nthr + tid] = X[k];
+      lds[(12 + k) * nthr + tid] = Y[k];
+    }
+    __syncthreads();
+    const int tm = (s > 0) ? tid - 1 : tid + Ls - 1;
+    const int tp = (s < Ls - 1) ? tid + 1 : tid - (Ls - 1);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) h[k] = X[k] + Y[k] + cu * lds[k * nthr + tm] + cl * lds[(12 + k) * nthr + tp];
+  }
+}
+
+template <int MU, int SGN, int PRE, int XM, typename R>
+__device__ inline void hop_dir(R *lds, int nthr, int tid, int s, int Ls, R cu, R cl, const R v[24], const R *U,
+                               R acc[24]) {
+  R h[12];
+  if (PRE)
+    project_pre<MU, SGN, XM>(lds, nthr, tid, s, Ls, cu, cl, v, h);
+  else
+    project<MU, SGN>(v, h);
+  hop_half<MU, SGN>(h, U, acc);
 }
 
 // ---------------------------------------------------------------- dense fifth-dimension matrices
@@ -214,25 +263,22 @@ __device__ inline void wg_partial(double *ldsd, int nthr, int tid, int Ls, int n
 // indexed by cb.  Otherwise (block domains) they are indexed by the position
 // in the list, and neighbours outside the domain point at the input list's
 // zero site, which is never written.
-template <int MU, int PLUS, typename R>
-__device__ inline void hop_term(const R v[24], const R u[18], R acc[24]) {
-  R h[12], w[12];
-  project<MU, PLUS ? 1 : -1>(v, h);
-  link_mul(u, h, w);
-  accumulate<MU, PLUS ? 1 : -1>(acc, w);
-}
+// Occupancy the register allocation of the hop kernel is held to (waves per SIMD).
+// (the LDS exchange keeps more values live; FP64 doubles every register)
+template <typename S, int XM> struct HopWaves { static constexpr int value = XM == kXLds ? 3 : 4; };
+template <int XM> struct HopWaves<double, XM> { static constexpr int value = 2; };
 
-template <typename S, int DAG, int PRE, int EPI, int DOT, int GLOBAL>
-__global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
+template <typename S, int DAG, int PRE, int EPI, int DOT, int GLOBAL, int XM>
+__global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(const HopArgs a) {
   using R = typename Traits<S>::R;
   extern __shared__ __align__(16) unsigned char smem[];
   const int Ls = a.Ls, nrhs = a.nrhs, nsw = a.nsite_wg;
   const int s = threadIdx.x, r = threadIdx.y, sl = threadIdx.z;
   const int nthr = Ls * nrhs * nsw;
   const int tid = s + Ls * (r + nrhs * sl);
-  R *lds = reinterpret_cast<R *>(smem);  // [24][nthr] fifth-dimension exchanges
-  R *Lk = lds + 24 * nthr;               // [nsite_wg][8][18] links of this workgroup's sites
-  R *Xl = Lk + nsw * 144;                // [2][Ls][Ls] dense epilogue matrix
+  R *Lk = reinterpret_cast<R *>(smem);  // [nsite_wg][8][18] links of this workgroup's sites
+  R *Xl = Lk + nsw * 144;               // [2][Ls][Ls] dense epilogue matrix
+  R *lds = Xl + (EPI == EPI_DENSE ? 2 * Ls * Ls : 0);  // [24][nthr] exchanges (LDS mode, dense epilogue)
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int site = tile * nsw + sl;
   const int cbr = (site < a.nsites) ? a.site_cb[site] : -1;
@@ -269,6 +315,11 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
   R acc[24];
   zero24(acc);
   const R *Lsite = Lk + sl * 144;
+  // PRE: the input is M_phi in = b (1 + (c/b) P_chi) in; the factor b goes
+  // into the final scale (handles are created only for b != 0)
+  const R pc = PRE ? (R)(a.mphi_c / a.mphi_b) : R(0);
+  const R pcu = pc * ((s > 0) ? R(1) : (R)(-a.mf));
+  const R pcl = pc * ((s < Ls - 1) ? R(1) : (R)(-a.mf));
   // One direction is always in flight ahead of the one being computed: the
   // forward neighbour of mu uses buffer `cur`, the backward one `nxt`.  The
   // loop over mu stays rolled on purpose (unrolled, the compiler hoists all
@@ -284,27 +335,30 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
       const int d = 2 * mu + bw;
       if (kPrefetch && bw == 1 && mu < 3) cur.load(in, a.in_norm, rin + (active ? nb[d + 1] : a.zero_site), s, Ls);
       if (!kPrefetch && d > 0) cur.load(in, a.in_norm, rin + (active ? nb[d] : a.zero_site), s, Ls);
-      R v[24], u[18];
+      R v[24];
       if (bw == 0 || !kPrefetch) cur.decode(v); else nxt.decode(v);
-      if (PRE) pchi_comb<0, R>(lds, nthr, tid, s, Ls, (R)a.mphi_b, (R)a.mphi_c, (R)a.mf, v);
-#pragma unroll
-      for (int k = 0; k < 18; ++k) u[k] = Lsite[d * 18 + k];
+      const R *U = Lsite + d * 18;
       // (1 - g_mu) for the forward hop of H and the backward hop of H^+
-      const bool plus = (bw != 0) == (DAG != 0);
+      constexpr int sp = (DAG != 0) ? -1 : 1;
+      const int sg = bw ? -sp : sp;
+#define MSPCG_DIR(M)                                                                   \
+  if (sg > 0) hop_dir<M, 1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, v, U, acc);      \
+  else hop_dir<M, -1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, v, U, acc);
       switch (mu) {
-        case 0: if (plus) hop_term<0, 1>(v, u, acc); else hop_term<0, 0>(v, u, acc); break;
-        case 1: if (plus) hop_term<1, 1>(v, u, acc); else hop_term<1, 0>(v, u, acc); break;
-        case 2: if (plus) hop_term<2, 1>(v, u, acc); else hop_term<2, 0>(v, u, acc); break;
-        default: if (plus) hop_term<3, 1>(v, u, acc); else hop_term<3, 0>(v, u, acc); break;
+        case 0: MSPCG_DIR(0) break;
+        case 1: MSPCG_DIR(1) break;
+        case 2: MSPCG_DIR(2) break;
+        default: MSPCG_DIR(3) break;
       }
+#undef MSPCG_DIR
     }
   }
 
-  const R scale = (R)a.scale;
+  const R scale = (R)(PRE ? a.scale * a.mphi_b : a.scale);
   if (EPI == EPI_DENSE) {
     dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * nsw, scale, acc);
   } else if (EPI == EPI_MPHIDAG || EPI == EPI_M5DAG_MPHIDAG) {
-    pchi_comb<1, R>(lds, nthr, tid, s, Ls, (R)a.mphi_b, (R)a.mphi_c, (R)a.mf, acc);
+    pchi_comb<1, XM, R>(lds, nthr, tid, s, Ls, (R)a.mphi_b, (R)a.mphi_c, (R)a.mf, acc);
 #pragma unroll
     for (int k = 0; k < 24; ++k) acc[k] *= scale;
   } else {
@@ -316,7 +370,8 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     R o[24];
     load24<R>(reinterpret_cast<const S *>(a.other), a.other_norm, (size_t)r * a.other_stride + oi, s, Ls, o);
     // M_5 = alpha - beta P_chi ; M_5^+ = alpha - beta P_chi^+
-    pchi_comb<EPI == EPI_M5DAG_MPHIDAG ? 1 : 0, R>(lds, nthr, tid, s, Ls, (R)a.m5_alpha, (R)(-a.m5_beta), (R)a.mf, o);
+    pchi_comb<EPI == EPI_M5DAG_MPHIDAG ? 1 : 0, XM, R>(lds, nthr, tid, s, Ls, (R)a.m5_alpha, (R)(-a.m5_beta), (R)a.mf,
+                                                     o);
 #pragma unroll
     for (int k = 0; k < 24; ++k) acc[k] += o[k];
   }
@@ -338,10 +393,11 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
 }
 
 template <typename S>
-static size_t hop_lds_bytes(const HopArgs &a, int nthr, int epi, int dot) {
+static size_t hop_lds_bytes(const HopArgs &a, int nthr, int epi, int dot, int xm) {
   using R = typename Traits<S>::R;
-  size_t b = ((size_t)24 * nthr + (size_t)144 * a.nsite_wg) * sizeof(R);
+  size_t b = (size_t)144 * a.nsite_wg * sizeof(R);
   if (epi == EPI_DENSE) b += (size_t)2 * a.Ls * a.Ls * sizeof(R);
+  if (epi == EPI_DENSE || xm == kXLds) b += (size_t)24 * nthr * sizeof(R);
   if (dot) b = std::max(b, (size_t)2 * nthr * sizeof(double));
   return b;
 }
@@ -351,8 +407,14 @@ static hipError_t launch_hop_t(const HopArgs &a, hipStream_t st) {
   const int nthr = a.nsite_wg * a.nrhs * a.Ls;
   const int grid = (a.nsites + a.nsite_wg - 1) / a.nsite_wg;
   if (nthr < 1 || nthr > 256 || grid < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((hop_kernel<S, DAG, PRE, EPI, DOT, GLOBAL>), dim3(grid), dim3(a.Ls, a.nrhs, a.nsite_wg),
-                     hop_lds_bytes<S>(a, nthr, EPI, DOT), st, a);
+  const dim3 blk(a.Ls, a.nrhs, a.nsite_wg);
+  const int xm = xmode(a.Ls);
+  const size_t lds = hop_lds_bytes<S>(a, nthr, EPI, DOT, xm);
+  switch (xm) {
+    case kXDpp16: hipLaunchKernelGGL((hop_kernel<S, DAG, PRE, EPI, DOT, GLOBAL, kXDpp16>), dim3(grid), blk, lds, st, a); break;
+    case kXPerm: hipLaunchKernelGGL((hop_kernel<S, DAG, PRE, EPI, DOT, GLOBAL, kXPerm>), dim3(grid), blk, lds, st, a); break;
+    default: hipLaunchKernelGGL((hop_kernel<S, DAG, PRE, EPI, DOT, GLOBAL, kXLds>), dim3(grid), blk, lds, st, a); break;
+  }
   return hipGetLastError();
 }
 
@@ -389,7 +451,7 @@ hipError_t launch_hop(int prec, int dagger, int pre, int epi, int dot, int globa
 }
 
 // ---------------------------------------------------------------- fifth-dimension operator
-template <typename S>
+template <typename S, int XM>
 __global__ void __launch_bounds__(256) op5_kernel(const Op5Args a) {
   using R = typename Traits<S>::R;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -411,10 +473,19 @@ __global__ void __launch_bounds__(256) op5_kernel(const Op5Args a) {
   if (a.dense)
     dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * a.nsite_wg, R(1), v);
   else if (a.dag)
-    pchi_comb<1, R>(lds, nthr, tid, s, Ls, (R)a.a, (R)a.b, (R)a.mf, v);
+    pchi_comb<1, XM, R>(lds, nthr, tid, s, Ls, (R)a.a, (R)a.b, (R)a.mf, v);
   else
-    pchi_comb<0, R>(lds, nthr, tid, s, Ls, (R)a.a, (R)a.b, (R)a.mf, v);
+    pchi_comb<0, XM, R>(lds, nthr, tid, s, Ls, (R)a.a, (R)a.b, (R)a.mf, v);
   if (active) store24<R>(reinterpret_cast<S *>(a.out), a.out_norm, idx, s, Ls, v);
+}
+
+template <typename S>
+static void launch_op5_t(const Op5Args &a, dim3 grid, dim3 blk, size_t lds, hipStream_t st) {
+  switch (xmode(a.Ls)) {
+    case kXDpp16: hipLaunchKernelGGL((op5_kernel<S, kXDpp16>), grid, blk, lds, st, a); break;
+    case kXPerm: hipLaunchKernelGGL((op5_kernel<S, kXPerm>), grid, blk, lds, st, a); break;
+    default: hipLaunchKernelGGL((op5_kernel<S, kXLds>), grid, blk, lds, st, a); break;
+  }
 }
 
 hipError_t launch_op5(int prec, const Op5Args &a, hipStream_t st) {
@@ -425,10 +496,10 @@ hipError_t launch_op5(int prec, const Op5Args &a, hipStream_t st) {
   const size_t lds = (24 * (size_t)nthr + 2 * (size_t)a.Ls * a.Ls) * rsz;
   const dim3 blk(a.Ls, a.nrhs, a.nsite_wg);
   switch (prec) {
-    case MSPCG_F64: hipLaunchKernelGGL(op5_kernel<double>, dim3(grid), blk, lds, st, a); break;
-    case MSPCG_F32: hipLaunchKernelGGL(op5_kernel<float>, dim3(grid), blk, lds, st, a); break;
-    case MSPCG_F16: hipLaunchKernelGGL(op5_kernel<_Float16>, dim3(grid), blk, lds, st, a); break;
-    case MSPCG_BF16: hipLaunchKernelGGL(op5_kernel<bf16>, dim3(grid), blk, lds, st, a); break;
+    case MSPCG_F64: launch_op5_t<double>(a, dim3(grid), blk, lds, st); break;
+    case MSPCG_F32: launch_op5_t<float>(a, dim3(grid), blk, lds, st); break;
+    case MSPCG_F16: launch_op5_t<_Float16>(a, dim3(grid), blk, lds, st); break;
+    case MSPCG_BF16: launch_op5_t<bf16>(a, dim3(grid), blk, lds, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -156,3 +156,14 @@ def test_conversions_round_trip(S):
     x[0, 3] = 0
     back = S.h.download(S.h.upload(x, 0, M.F16))
     assert np.all(back[0, 3] == 0) and np.isfinite(back).all()
+
+
+def test_create_rejects_zero_b():
+    """The hop kernels factor b out of M_phi = b + c P_chi: b = 0 is refused at create."""
+    require_gpu()
+    from paper_1811_08488_amd import synth
+
+    L = (4, 4, 4, 4)
+    with pytest.raises(M.MspcgError) as e:
+        M.Handle(M.Action(L, 4, M5=1.8, mf=0.1, b=0.0, c=0.5), synth.gauge_field(L, 0.3, 1))
+    assert e.value.status == M.EUNSUPPORTED
