@@ -29,8 +29,9 @@ __device__ inline void zero24(R v[24]) {
 //    VALU instruction stream, with no LDS traffic and no barrier;
 //  * Ls divides 64: groups never straddle a wavefront; ds_bpermute;
 //  * otherwise (Ls = 12, 24, ...): through LDS with workgroup barriers.
-__device__ inline int rot_prev_dpp(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x121, 0xF, 0xF, false); }
-__device__ inline int rot_next_dpp(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x12F, 0xF, 0xF, false); }
+// (row_ror with all rows and banks enabled writes every lane: no "old" value)
+__device__ inline int rot_prev_dpp(int x) { return __builtin_amdgcn_mov_dpp(x, 0x121, 0xF, 0xF, false); }
+__device__ inline int rot_next_dpp(int x) { return __builtin_amdgcn_mov_dpp(x, 0x12F, 0xF, 0xF, false); }
 __device__ inline float rot_prev_dpp(float x) { return __builtin_bit_cast(float, rot_prev_dpp(__builtin_bit_cast(int, x))); }
 __device__ inline float rot_next_dpp(float x) { return __builtin_bit_cast(float, rot_next_dpp(__builtin_bit_cast(int, x))); }
 __device__ inline double rot_prev_dpp(double x) {
@@ -96,35 +97,46 @@ __device__ inline void pchi_comb(R *lds, int nthr, int tid, int s, int Ls, R a, 
 // Projected half spinor of (1 + pc P_chi) v for the hop in direction MU:
 // h(s) = X(s) + Y(s) + cu X(s-1) + cl Y(s+1) with X, Y the two parts of the
 // projection (P_chi takes the upper spins from s-1 and the lower ones from
-// s+1, with the -mf corners folded into cu, cl).  Projecting before the
-// exchange moves 12 + 12 reals instead of 24 and needs no full M_phi v.
+// s+1, with the -mf corners folded into cu, cl), so no full M_phi v is formed.
 // Must be reached by all threads of the workgroup.
 template <int MU, int SGN, int XM, typename R>
 __device__ inline void project_pre(R *lds, int nthr, int tid, int s, int Ls, R cu, R cl, const R v[24], R h[12]) {
-  R X[12], Y[12];
-  project_parts<MU, SGN>(v, X, Y);
+  // w: the upper spins of v at s-1 and the lower spins at s+1 (rotated raw, so
+  // that the signs of the projection fold into the multiply-adds)
+  R w[24];
   if (XM == kXDpp16) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) h[k] = X[k] + Y[k] + cu * rot_prev_dpp(X[k]) + cl * rot_next_dpp(Y[k]);
+    for (int k = 0; k < 12; ++k) {
+      w[k] = rot_prev_dpp(v[k]);
+      w[12 + k] = rot_next_dpp(v[12 + k]);
+    }
   } else if (XM == kXPerm) {
     const int lane = tid & 63;
     const int am = 4 * ((s > 0) ? lane - 1 : lane + Ls - 1);
     const int ap = 4 * ((s < Ls - 1) ? lane + 1 : lane - (Ls - 1));
 #pragma unroll
-    for (int k = 0; k < 12; ++k) h[k] = X[k] + Y[k] + cu * perm(am, X[k]) + cl * perm(ap, Y[k]);
+    for (int k = 0; k < 12; ++k) {
+      w[k] = perm(am, v[k]);
+      w[12 + k] = perm(ap, v[12 + k]);
+    }
   } else {
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      lds[k * nthr + tid] = X[k];
-      lds[(12 + k) * nthr + tid] = Y[k];
-    }
+    for (int k = 0; k < 24; ++k) lds[k * nthr + tid] = v[k];
     __syncthreads();
     const int tm = (s > 0) ? tid - 1 : tid + Ls - 1;
     const int tp = (s < Ls - 1) ? tid + 1 : tid - (Ls - 1);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) h[k] = X[k] + Y[k] + cu * lds[k * nthr + tm] + cl * lds[(12 + k) * nthr + tp];
+    for (int k = 0; k < 12; ++k) {
+      w[k] = lds[k * nthr + tm];
+      w[12 + k] = lds[(12 + k) * nthr + tp];
+    }
   }
+  R X[12], Y[12], Xw[12], Yw[12];
+  project_parts<MU, SGN>(v, X, Y);
+  project_parts<MU, SGN>(w, Xw, Yw);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) h[k] = fma(cl, Yw[k], fma(cu, Xw[k], X[k] + Y[k]));
 }
 
 template <int MU, int SGN, int PRE, int XM, typename R>

@@ -216,6 +216,29 @@ class Handle:
         torch.cuda.synchronize()
         return from_device_layout(f.data.cpu().numpy(), f.nrhs, self.A.V // 2, self.A.Ls)
 
+    def write_sites(self, f: Field, cb, values):
+        """Write complex128 [nrhs, n, Ls, 4, 3] into the listed cb sites of an F64 field."""
+        torch = _torch()
+        if f.prec != F64:
+            raise ValueError("write_sites needs an F64 field")
+        cb = np.asarray(cb, dtype=np.int64)
+        v = to_device_layout(np.ascontiguousarray(values, dtype=np.complex128)).reshape(
+            f.nrhs, len(cb), 12, self.A.Ls, 2)
+        view = f.data.view(f.nrhs, self.A.V // 2, 12, self.A.Ls, 2)
+        view[:, torch.from_numpy(cb).to(f.data.device)] = torch.from_numpy(v).to(f.data.device)
+
+    def read_sites(self, f: Field, cb) -> np.ndarray:
+        """The listed cb sites of a field as complex128 [nrhs, n, Ls, 4, 3]."""
+        torch = _torch()
+        if f.prec != F64:
+            t = self.field(F64, f.nrhs, f.parity)
+            self.convert(t, f)
+            f = t
+        cb = np.asarray(cb, dtype=np.int64)
+        view = f.data.view(f.nrhs, self.A.V // 2, 12, self.A.Ls, 2)
+        got = view[:, torch.from_numpy(cb).to(f.data.device)].cpu().numpy()
+        return from_device_layout(got.reshape(-1), f.nrhs, len(cb), self.A.Ls)
+
     # -------------------------------------------------------- operators
     def convert(self, out: Field, inp: Field, stream=None):
         _check(lib().mspcg_convert(self.h, ctypes.byref(out.c()), ctypes.byref(inp.c()), _stream(stream)))
