@@ -173,6 +173,33 @@ def kernels_only(w, torch):
           flush=True)
 
 
+def study(w, torch, ks=(3, 4, 6, 8, 12, 18), inner_prec=None):
+    """Inner-iteration sweep with and without the snake terms (Sec. 2.3, Sec. 3):
+    outer iterations and time-to-solution for each k, plain CG for reference."""
+    h, A, U, eps, b = build_problem(w, torch)
+    x = h.field(M.F64, w.nrhs, 0)
+    prec = PREC[inner_prec or w.inner_prec]
+    rows = []
+    x.data.zero_()
+    st = h.cg_solve(x, b, tol=w.tol, max_iter=50000, reliable=w.reliable)
+    rows.append({"solver": "cg", "outer_iters": st["outer_iters"], "seconds": st["seconds"],
+                 "true_rel_resid": st["true_rel_resid"]})
+    log(f"[study] plain CG: {st['outer_iters']} iterations, {st['seconds']:.3f}s")
+    for no_snake in (0, 1):
+        for k in ks:
+            for rep in range(2):  # the first solve of a shape tunes and captures
+                x.data.zero_()
+                st = h.mspcg_solve(x, b, w.nblk, k, prec, tol=w.tol, max_iter=20000, reliable=w.reliable,
+                                   no_snake=no_snake)
+            rows.append({"solver": "mspcg", "k": k, "snake_terms": not no_snake, "status": st["status"],
+                         "outer_iters": st["outer_iters"], "seconds": st["seconds"],
+                         "true_rel_resid": st["true_rel_resid"]})
+            log(f"[study] k={k} snake={not no_snake}: {st['outer_iters']} outer, {st['seconds']:.3f}s")
+    print(json.dumps({"study": "inner iterations and snake terms", "workload": w.name,
+                      "inner_prec": inner_prec or w.inner_prec, "blocks": list(w.nblk), "tol": w.tol, "rows": rows}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,6 +210,8 @@ def main():
     ap.add_argument("--n-inner", type=int, default=None)
     ap.add_argument("--cg-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--study", action="store_true",
+                    help="sweep the inner iterations k with and without the snake terms instead of the benchmark")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only launch dslash_eo (F64/F32/F16) and a plain F64 copy of the same size, 10 times each "
                          "(the workload for hardware-counter runs)")
@@ -202,6 +231,9 @@ def main():
     nblk = w.nblk
     if args.kernels_only:
         kernels_only(w, torch)
+        return
+    if args.study:
+        study(w, torch, inner_prec=args.inner_prec)
         return
     h, A, U, eps, b = build_problem(w, torch)
     x = h.field(M.F64, w.nrhs, 0)

@@ -96,6 +96,9 @@ typedef struct {
   int nblk[4];           /* Dirichlet blocks per dimension (uneven splits allowed) */
   int n_inner;           /* fixed number k of inner CG iterations (>= 0) */
   mspcg_prec inner_prec; /* storage of the inner solve: F32, F16 or BF16 (F64 allowed for tests) */
+  int no_snake;          /* 0 (default): A_s = P_s A P_s with its snake terms (Sec. 2.3);
+                          * 1: every hop cut at the block boundary (P_s H P_s), which drops
+                          * the snake terms -- the variant Sec. 2.3 argues against, for comparison */
 } mspcg_precond;
 
 typedef struct {
@@ -147,9 +150,10 @@ mspcg_status local_block_cg(mspcg_handle *h, mspcg_field *z, const mspcg_field *
 
 /* One application of the preconditioner's operator: out = (direct sum over
  * blocks s of A_s) in, with A_s = P_s A P_s including its snake terms
- * (Sec. 2.3), computed on the halo-extended block domains with storage
- * `prec` (FP32 arithmetic unless F64).  in/out: even F64 fields. */
-mspcg_status mspcg_block_apply(mspcg_handle *h, mspcg_field *out, const mspcg_field *in, const int nblk[4], int prec,
+ * (Sec. 2.3; pc->no_snake = 1: the truncated variant), computed on the
+ * halo-extended block domains with storage pc->inner_prec (FP32 arithmetic
+ * unless F64); pc->n_inner is ignored.  in/out: even F64 fields. */
+mspcg_status mspcg_block_apply(mspcg_handle *h, mspcg_field *out, const mspcg_field *in, const mspcg_precond *pc,
                                void *stream);
 
 /* Plain CG (Algorithm 1 with M = 1) on A x = b, FP64.  x: initial guess in,

@@ -91,6 +91,7 @@ struct OwnedVec {
 // keeps every path of the four hops that leaves the block and comes back).
 struct BlockGeom {
   int nblk[4];
+  int no_snake = 0;  // 1: every hop cut at the block boundary (O1 = odd, E2 = even sites of the block)
   int nb = 0;
   int be_tot = 0, o1_tot = 0, e2_tot = 0;
   std::vector<int> be_off, o1_off, e2_off;   // padded offsets, size nb+1
@@ -377,18 +378,24 @@ void ensure_fp64_temps(mspcg_handle *h, int nrhs) {
 }
 
 // ------------------------------------------------------------- block geometry
-BlockGeom *get_blocks(mspcg_handle *h, const int nblk[4], hipStream_t st) {
+// no_snake = 0: the domains of A_s = P_s A P_s with its snake terms (halo of
+// depth 2); no_snake = 1: the block alone, every hop cut at its boundary
+// (P_s H P_s), which drops the snake terms.
+BlockGeom *get_blocks(mspcg_handle *h, const int nblk[4], int no_snake, hipStream_t st) {
   std::vector<int> key(nblk, nblk + 4);
+  key.push_back(no_snake ? 1 : 0);
   auto it = h->blocks.find(key);
   if (it != h->blocks.end()) return it->second.get();
   const int *L = h->par.L;
+  const int depth = no_snake ? 0 : 2;  // halo of the extended domains
   for (int mu = 0; mu < 4; ++mu) {
     if (nblk[mu] < 1 || nblk[mu] > L[mu]) fail(MSPCG_EINVAL, "nblk out of range");
-    if (nblk[mu] >= 2 && L[mu] / nblk[mu] + (L[mu] % nblk[mu] ? 1 : 0) + 4 > L[mu])
+    if (nblk[mu] >= 2 && L[mu] / nblk[mu] + (L[mu] % nblk[mu] ? 1 : 0) + 2 * depth > L[mu])
       fail(MSPCG_EUNSUPPORTED, "block halo of depth 2 would wrap onto itself (need L >= block + 4)");
   }
   auto bg = std::make_unique<BlockGeom>();
   std::memcpy(bg->nblk, nblk, sizeof(bg->nblk));
+  bg->no_snake = no_snake ? 1 : 0;
   bg->nb = nblk[0] * nblk[1] * nblk[2] * nblk[3];
   const int V = h->V;
   std::vector<int> e2_of_lex(V, -1), o1_of_lex(V, -1);  // per-block scratch maps
@@ -405,8 +412,8 @@ BlockGeom *get_blocks(mspcg_handle *h, const int nblk[4], hipStream_t st) {
       const int q = L[mu] / nblk[mu], rr = L[mu] % nblk[mu];
       start[mu] = jb[mu] * q + std::min(jb[mu], rr);
       size[mu] = q + (jb[mu] < rr ? 1 : 0);
-      lo[mu] = nblk[mu] >= 2 ? -2 : 0;
-      hi[mu] = nblk[mu] >= 2 ? size[mu] + 2 : size[mu];
+      lo[mu] = nblk[mu] >= 2 ? -depth : 0;
+      hi[mu] = nblk[mu] >= 2 ? size[mu] + depth : size[mu];
     }
     // enumerate the extended box in local lex order (x fastest)
     std::vector<int> loc_be, loc_o1, loc_e2;
@@ -423,11 +430,11 @@ BlockGeom *get_blocks(mspcg_handle *h, const int nblk[4], hipStream_t st) {
             }
             const int g = lex_of(c);
             const int par = (c[0] + c[1] + c[2] + c[3]) & 1;
-            if (par == 0 && dist <= 2) {
+            if (par == 0 && dist <= depth) {
               loc_e2.push_back(g);
               dist_e2.push_back(dist);
             }
-            if (par == 1 && dist <= 1) loc_o1.push_back(g);
+            if (par == 1 && dist <= depth / 2) loc_o1.push_back(g);
             if (par == 0 && dist == 0) loc_be.push_back(g);
           }
     const int be0 = bg->be_off.back(), o10 = bg->o1_off.back(), e20 = bg->e2_off.back();
@@ -700,7 +707,7 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
     hipStream_t st = h->work;
     const int nrhs = b->nrhs, Ls = h->par.Ls;
     const long long n = (long long)h->Vh * Ls * 24;
-    BlockGeom *bg = pc ? get_blocks(h, pc->nblk, st) : nullptr;
+    BlockGeom *bg = pc ? get_blocks(h, pc->nblk, pc->no_snake, st) : nullptr;
     ensure_fp64_temps(h, nrhs);
     h->sr.ensure(MSPCG_F64, nrhs, h->Vh, Ls);
     h->sp.ensure(MSPCG_F64, nrhs, h->Vh, Ls);
@@ -1041,7 +1048,7 @@ mspcg_status local_block_cg(mspcg_handle *h, mspcg_field *z, const mspcg_field *
     if (pc->n_inner < 0) fail(MSPCG_EINVAL, "n_inner < 0");
     if (pc->inner_prec < MSPCG_F64 || pc->inner_prec > MSPCG_BF16) fail(MSPCG_EINVAL, "bad inner precision");
     hipStream_t st = S(stream);
-    BlockGeom *bg = get_blocks(h, pc->nblk, st);
+    BlockGeom *bg = get_blocks(h, pc->nblk, pc->no_snake, st);
     const int nrhs = r->nrhs;
     const long long n = (long long)h->Vh * h->par.Ls * 24;
     ensure_block_vecs(h, bg, pc->inner_prec, nrhs);
@@ -1156,7 +1163,7 @@ mspcg_status mspcg_debug_block_sites(mspcg_handle *h, const int nblk[4], int blo
                                      int32_t *o1_lex, int32_t *e2_lex) {
   return guarded([&] {
     if (!h || !nblk || !counts) fail(MSPCG_EINVAL, "NULL argument");
-    BlockGeom *bg = get_blocks(h, nblk, h->stream);
+    BlockGeom *bg = get_blocks(h, nblk, 0, h->stream);
     if (block < 0 || block >= bg->nb) fail(MSPCG_EINVAL, "block out of range");
     counts[0] = bg->be_n[block];
     counts[1] = bg->o1_n[block];
@@ -1167,19 +1174,20 @@ mspcg_status mspcg_debug_block_sites(mspcg_handle *h, const int nblk[4], int blo
   });
 }
 
-mspcg_status mspcg_block_apply(mspcg_handle *h, mspcg_field *out, const mspcg_field *in, const int nblk[4], int prec,
+mspcg_status mspcg_block_apply(mspcg_handle *h, mspcg_field *out, const mspcg_field *in, const mspcg_precond *pc,
                                void *stream) {
   return guarded([&] {
-    if (!h || !nblk) fail(MSPCG_EINVAL, "NULL argument");
+    if (!h || !pc) fail(MSPCG_EINVAL, "NULL argument");
     check_field(h, out, "out");
     check_field(h, in, "in");
     if (out->prec != MSPCG_F64 || in->prec != MSPCG_F64) fail(MSPCG_EINVAL, "mspcg_block_apply takes F64 fields");
     if (out->parity != 0 || in->parity != 0) fail(MSPCG_EINVAL, "mspcg_block_apply works on even sites");
     if (out->nrhs != in->nrhs) fail(MSPCG_EINVAL, "nrhs mismatch");
+    const int prec = pc->inner_prec;
     if (prec < MSPCG_F64 || prec > MSPCG_BF16) fail(MSPCG_EINVAL, "bad precision");
     if (out->data == in->data) fail(MSPCG_EINVAL, "out must not alias in");
     hipStream_t st = S(stream);
-    BlockGeom *bg = get_blocks(h, nblk, st);
+    BlockGeom *bg = get_blocks(h, pc->nblk, pc->no_snake, st);
     const int nrhs = in->nrhs;
     ensure_links(h, prec, st);
     ensure_block_vecs(h, bg, prec, nrhs);

@@ -38,7 +38,8 @@ class CField(ctypes.Structure):
 
 
 class Precond(ctypes.Structure):
-    _fields_ = [("nblk", ctypes.c_int * 4), ("n_inner", ctypes.c_int), ("inner_prec", ctypes.c_int)]
+    _fields_ = [("nblk", ctypes.c_int * 4), ("n_inner", ctypes.c_int), ("inner_prec", ctypes.c_int),
+                ("no_snake", ctypes.c_int)]
 
 
 class Solver(ctypes.Structure):
@@ -78,7 +79,7 @@ def lib():
             "mspcg_debug_site_maps": [P, I, P, P],
             "mspcg_debug_block_sites": [P, P, I, P, P, P, P],
             "mspcg_convert": [P, FP, FP, P],
-            "mspcg_block_apply": [P, FP, FP, P, I, P],
+            "mspcg_block_apply": [P, FP, FP, ctypes.POINTER(Precond), P],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -252,13 +253,13 @@ class Handle:
     def mdagm(self, out: Field, inp: Field, stream=None):
         _check(lib().mdagm(self.h, ctypes.byref(out.c()), ctypes.byref(inp.c()), _stream(stream)))
 
-    def block_apply(self, out: Field, inp: Field, nblk, prec=F64, stream=None):
-        nb = (ctypes.c_int * 4)(*nblk)
-        _check(lib().mspcg_block_apply(self.h, ctypes.byref(out.c()), ctypes.byref(inp.c()), nb, int(prec),
+    def block_apply(self, out: Field, inp: Field, nblk, prec=F64, stream=None, no_snake=0):
+        pc = Precond((ctypes.c_int * 4)(*nblk), 0, int(prec), int(no_snake))
+        _check(lib().mspcg_block_apply(self.h, ctypes.byref(out.c()), ctypes.byref(inp.c()), ctypes.byref(pc),
                                        _stream(stream)))
 
-    def local_block_cg(self, z: Field, r: Field, nblk, n_inner, inner_prec=F32, stream=None):
-        pc = Precond((ctypes.c_int * 4)(*nblk), int(n_inner), int(inner_prec))
+    def local_block_cg(self, z: Field, r: Field, nblk, n_inner, inner_prec=F32, stream=None, no_snake=0):
+        pc = Precond((ctypes.c_int * 4)(*nblk), int(n_inner), int(inner_prec), int(no_snake))
         _check(lib().local_block_cg(self.h, ctypes.byref(z.c()), ctypes.byref(r.c()), ctypes.byref(pc),
                                     _stream(stream)))
 
@@ -278,8 +279,8 @@ class Handle:
         if precond is None:
             rc = lib().cg_solve(self.h, ctypes.byref(x.c()), ctypes.byref(b.c()), ctypes.byref(s), ctypes.byref(st))
         else:
-            nblk, k, prec = precond
-            pc = Precond((ctypes.c_int * 4)(*nblk), int(k), int(prec))
+            nblk, k, prec, no_snake = precond
+            pc = Precond((ctypes.c_int * 4)(*nblk), int(k), int(prec), int(no_snake))
             rc = lib().mspcg_solve(self.h, ctypes.byref(x.c()), ctypes.byref(b.c()), ctypes.byref(s),
                                    ctypes.byref(pc), ctypes.byref(st))
         _check(rc, allow=(OK, NOT_CONVERGED))
@@ -290,8 +291,8 @@ class Handle:
         return self._solve(x, b, tol, max_iter, reliable, None)
 
     def mspcg_solve(self, x: Field, b: Field, nblk, n_inner, inner_prec=F32, tol=1e-10, max_iter=10000,
-                    reliable=50, use_graph=1):
-        return self._solve(x, b, tol, max_iter, reliable, (nblk, n_inner, inner_prec), use_graph)
+                    reliable=50, use_graph=1, no_snake=0):
+        return self._solve(x, b, tol, max_iter, reliable, (nblk, n_inner, inner_prec, no_snake), use_graph)
 
     # -------------------------------------------------------- debug exports
     def site_maps(self, parity):

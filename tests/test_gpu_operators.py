@@ -113,9 +113,9 @@ def test_mdagm_shamir(S_shamir):
     assert rel(S.h.download(fout)[0], O.mdagm(S.oa, S.U, x[0])) <= 1e-13
 
 
-def _oracle_block_sum(S, x, nblk):
+def _oracle_block_sum(S, x, nblk, truncated=False):
     nb = int(np.prod(nblk))
-    return sum(O.block_op(S.oa, S.U, x, nblk, b) for b in range(nb))
+    return sum(O.block_op(S.oa, S.U, x, nblk, b, truncated) for b in range(nb))
 
 
 @pytest.mark.parametrize("prec", PRECS, ids=lambda p: PNAME[p])
@@ -128,6 +128,22 @@ def test_block_apply(L, Ls, nblk, prec):
     S.h.block_apply(fout, S.h.upload(x, 0), nblk, prec)
     want = _oracle_block_sum(S, x[0], nblk)
     assert rel(S.h.download(fout)[0], want) <= TOL[prec], (PNAME[prec], rel(S.h.download(fout)[0], want))
+
+
+@pytest.mark.parametrize("prec", [M.F64, M.F32], ids=lambda p: PNAME[p])
+@pytest.mark.parametrize("L,Ls,nblk", [((8, 8, 8, 8), 8, (2, 2, 2, 2)), ((10, 8, 6, 12), 4, (3, 2, 1, 2))])
+def test_block_apply_without_snake_terms(L, Ls, nblk, prec):
+    """Every hop cut at the block boundary (the variant Sec. 2.3 compares against)."""
+    require_gpu()
+    S = Setup(L, Ls, "mobius", seed=6)
+    x = S.rand(1, 51)
+    fout = S.h.field(M.F64, 1, 0)
+    S.h.block_apply(fout, S.h.upload(x, 0), nblk, prec, no_snake=1)
+    got = S.h.download(fout)[0]
+    want = _oracle_block_sum(S, x[0], nblk, truncated=True)
+    assert rel(got, want) <= TOL[prec]
+    # and it differs from the operator with the snake terms
+    assert rel(got, _oracle_block_sum(S, x[0], nblk)) > 1e-3
 
 
 def test_prepare_and_reconstruct(S):

@@ -59,6 +59,27 @@ def test_local_block_cg_scale_invariance(S):
         assert rel(z, want) <= 3e-2
 
 
+@pytest.mark.parametrize("k", [1, 3])
+def test_local_block_cg_without_snake_terms(S, k):
+    nblk = SMALL[2]
+    r = S.rand(1, 75 + k)
+    fz = S.h.field(M.F64, 1, 0)
+    S.h.local_block_cg(fz, S.h.upload(r, 0), nblk, k, M.F64, no_snake=1)
+    want = O.local_block_cg(S.oa, S.U, r[0], nblk, k, truncated=True)
+    assert rel(S.h.download(fz)[0], want) <= 1e-11
+
+
+def test_mspcg_without_snake_terms_matches_oracle(S):
+    nblk = SMALL[2]
+    b = S.rand(1, 97)[0]
+    xo, st_o = O.solve(S.oa, S.U, b, nblk=nblk, k=3, truncated=True, tol=1e-10, maxiter=2000)
+    fx = S.h.field(M.F64, 1, 0)
+    st = S.h.mspcg_solve(fx, S.h.upload(b, 0), nblk, 3, M.F64, tol=1e-10, no_snake=1)
+    assert st["status"] == M.OK
+    assert rel(S.h.download(fx)[0], xo) <= 1e-8
+    assert abs(st["outer_iters"] - st_o.iters) <= 2 + 0.02 * st_o.iters
+
+
 def _true_resid(S, x, b):
     return float(np.linalg.norm(b - O.mdagm(S.oa, S.U, x)) / np.linalg.norm(b))
 
