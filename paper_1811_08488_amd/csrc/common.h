@@ -197,6 +197,21 @@ template <> struct RawSite<float> {
 template <> struct RawSite<_Float16> {
   uint4 c[3];
   float n;
+  __device__ uint32_t word(int i) const { return i < 4 ? (&c[0].x)[i] : i < 8 ? (&c[1].x)[i - 4] : (&c[2].x)[i - 8]; }
+  __device__ void set_word(int i, uint32_t w) {
+    if (i < 4) (&c[0].x)[i] = w; else if (i < 8) (&c[1].x)[i - 4] = w; else (&c[2].x)[i - 8] = w;
+  }
+  // the stored values without the norm (each widened once, where it is used)
+  __device__ void decode_raw(float v[24]) const {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      const uint32_t w = word(i);
+      union { uint32_t u; _Float16 h[2]; } t;
+      t.u = w;
+      v[2 * i] = (float)t.h[0];
+      v[2 * i + 1] = (float)t.h[1];
+    }
+  }
   __device__ void load(const _Float16 *base, const float *norm, size_t site4, int s, int Ls) {
     n = norm[site4 * Ls + s];
 #pragma unroll
@@ -219,6 +234,18 @@ template <> struct RawSite<_Float16> {
 template <> struct RawSite<bf16> {
   uint4 c[3];
   float n;
+  __device__ uint32_t word(int i) const { return i < 4 ? (&c[0].x)[i] : i < 8 ? (&c[1].x)[i - 4] : (&c[2].x)[i - 8]; }
+  __device__ void set_word(int i, uint32_t w) {
+    if (i < 4) (&c[0].x)[i] = w; else if (i < 8) (&c[1].x)[i - 4] = w; else (&c[2].x)[i - 8] = w;
+  }
+  __device__ void decode_raw(float v[24]) const {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      const uint32_t w = word(i);
+      v[2 * i] = bf16_to_float((uint16_t)(w & 0xffffu));
+      v[2 * i + 1] = bf16_to_float((uint16_t)(w >> 16));
+    }
+  }
   __device__ void load(const bf16 *base, const float *norm, size_t site4, int s, int Ls) {
     n = norm[site4 * Ls + s];
 #pragma unroll
@@ -383,9 +410,11 @@ __device__ inline void link_mul(const R u[18], const R h[12], R w[12]) {
 // acc += (w, -SGN B^+ w) for one colour c: B_x^+ w = (i w1, i w0),
 // B_y^+ w = (w1, -w0), B_z^+ w = (i w0, -i w1), B_t^+ w = (w0, w1).
 template <int MU, int SGN, typename R>
-__device__ inline void accumulate_colour(R acc[24], int c, R w0r, R w0i, R w1r, R w1i) {
-  acc[(0 * 3 + c) * 2] += w0r; acc[(0 * 3 + c) * 2 + 1] += w0i;
-  acc[(1 * 3 + c) * 2] += w1r; acc[(1 * 3 + c) * 2 + 1] += w1i;
+__device__ inline void accumulate_colour(R acc[24], int c, R w0r, R w0i, R w1r, R w1i, R n) {
+  // acc += n w: n is the per-site norm of F16/BF16 inputs (1 otherwise), so
+  // the additions are multiply-adds of the same cost
+  acc[(0 * 3 + c) * 2] = fma(n, w0r, acc[(0 * 3 + c) * 2]); acc[(0 * 3 + c) * 2 + 1] = fma(n, w0i, acc[(0 * 3 + c) * 2 + 1]);
+  acc[(1 * 3 + c) * 2] = fma(n, w1r, acc[(1 * 3 + c) * 2]); acc[(1 * 3 + c) * 2 + 1] = fma(n, w1i, acc[(1 * 3 + c) * 2 + 1]);
   R l0r, l0i, l1r, l1i;  // -SGN B^+ w
   if (MU == 0) {
     l0r = SGN * w1i; l0i = -SGN * w1r;
@@ -400,8 +429,8 @@ __device__ inline void accumulate_colour(R acc[24], int c, R w0r, R w0i, R w1r, 
     l0r = -SGN * w0r; l0i = -SGN * w0i;
     l1r = -SGN * w1r; l1i = -SGN * w1i;
   }
-  acc[(2 * 3 + c) * 2] += l0r; acc[(2 * 3 + c) * 2 + 1] += l0i;
-  acc[(3 * 3 + c) * 2] += l1r; acc[(3 * 3 + c) * 2 + 1] += l1i;
+  acc[(2 * 3 + c) * 2] = fma(n, l0r, acc[(2 * 3 + c) * 2]); acc[(2 * 3 + c) * 2 + 1] = fma(n, l0i, acc[(2 * 3 + c) * 2 + 1]);
+  acc[(3 * 3 + c) * 2] = fma(n, l1r, acc[(3 * 3 + c) * 2]); acc[(3 * 3 + c) * 2 + 1] = fma(n, l1i, acc[(3 * 3 + c) * 2 + 1]);
 }
 
 template <int MU, int SGN, typename R>
@@ -409,7 +438,7 @@ __device__ inline void accumulate(R acc[24], const R w[12]) {
 #pragma unroll
   for (int c = 0; c < 3; ++c)
     accumulate_colour<MU, SGN>(acc, c, w[(0 * 3 + c) * 2], w[(0 * 3 + c) * 2 + 1], w[(1 * 3 + c) * 2],
-                               w[(1 * 3 + c) * 2 + 1]);
+                               w[(1 * 3 + c) * 2 + 1], R(1));
 }
 
 // One direction of the hop for one 5D site, given the projected neighbour
@@ -418,7 +447,7 @@ __device__ inline void accumulate(R acc[24], const R w[12]) {
 // straight away, so that only the accumulator, the half spinor and one link
 // row are live.
 template <int MU, int SGN, typename R>
-__device__ inline void hop_half(const R h[12], const R *U, R acc[24]) {
+__device__ inline void hop_half(const R h[12], const R *U, R acc[24], R n) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     R ur[6];
@@ -442,7 +471,7 @@ __device__ inline void hop_half(const R h[12], const R *U, R acc[24]) {
       w[2 * k] = re;
       w[2 * k + 1] = im;
     }
-    accumulate_colour<MU, SGN>(acc, a, w[0], w[1], w[2], w[3]);
+    accumulate_colour<MU, SGN>(acc, a, w[0], w[1], w[2], w[3], n);
   }
 }
 

@@ -147,7 +147,77 @@ __device__ inline void hop_dir(R *lds, int nthr, int tid, int s, int Ls, R cu, R
     project_pre<MU, SGN, XM>(lds, nthr, tid, s, Ls, cu, cl, v, h);
   else
     project<MU, SGN>(v, h);
-  hop_half<MU, SGN>(h, U, acc);
+  hop_half<MU, SGN>(h, U, acc, R(1));
+}
+
+__device__ inline uint32_t rot_prev_word(uint32_t x) { return (uint32_t)rot_prev_dpp((int)x); }
+__device__ inline uint32_t rot_next_word(uint32_t x) { return (uint32_t)rot_next_dpp((int)x); }
+
+// The same for F16/BF16 inputs stored as v/n with a per-site norm n: the
+// projection works on the stored values (for F16 every widening folds into a
+// mixed-precision multiply-add, `one` being an opaque 1 that keeps the sum a
+// multiply-add) and n multiplies the link product as it is accumulated.  With
+// M_phi on the input the neighbours' norms enter the mixing coefficients as
+// n(s -+ 1)/n(s) (a zero site has no stored values and uses n = 1).
+template <int MU, int SGN, int PRE, int XM, typename S>
+__device__ inline void hop_dir_norm(float *lds, int nthr, int tid, int s, int Ls, float cu, float cl, float one,
+                                    const RawSite<S> &raw, const float *U, float acc[24]) {
+  float v[24], X[12], Y[12], h[12];
+  raw.decode_raw(v);
+  project_parts<MU, SGN>(v, X, Y);
+  float n = raw.n;
+  if (PRE) {
+    RawSite<S> w;  // the upper spins at s-1 and the lower spins at s+1, as stored
+    float nm, np;
+    if (XM == kXDpp16) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        w.set_word(i, rot_prev_word(raw.word(i)));
+        w.set_word(6 + i, rot_next_word(raw.word(6 + i)));
+      }
+      nm = rot_prev_dpp(n);
+      np = rot_next_dpp(n);
+    } else if (XM == kXPerm) {
+      const int lane = tid & 63;
+      const int am = 4 * ((s > 0) ? lane - 1 : lane + Ls - 1);
+      const int ap = 4 * ((s < Ls - 1) ? lane + 1 : lane - (Ls - 1));
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        w.set_word(i, (uint32_t)__builtin_amdgcn_ds_bpermute(am, (int)raw.word(i)));
+        w.set_word(6 + i, (uint32_t)__builtin_amdgcn_ds_bpermute(ap, (int)raw.word(6 + i)));
+      }
+      nm = perm(am, n);
+      np = perm(ap, n);
+    } else {
+      uint32_t *lw = reinterpret_cast<uint32_t *>(lds);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 12; ++i) lw[i * nthr + tid] = raw.word(i);
+      lds[12 * nthr + tid] = n;
+      __syncthreads();
+      const int tm = (s > 0) ? tid - 1 : tid + Ls - 1;
+      const int tp = (s < Ls - 1) ? tid + 1 : tid - (Ls - 1);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        w.set_word(i, lw[i * nthr + tm]);
+        w.set_word(6 + i, lw[(6 + i) * nthr + tp]);
+      }
+      nm = lds[12 * nthr + tm];
+      np = lds[12 * nthr + tp];
+    }
+    float wv[24], Xw[12], Yw[12];
+    w.decode_raw(wv);
+    project_parts<MU, SGN>(wv, Xw, Yw);
+    n = n > 0.f ? n : 1.f;
+    const float rn = __builtin_amdgcn_rcpf(n);
+    const float cu2 = cu * nm * rn, cl2 = cl * np * rn;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) h[k] = fmaf(cl2, Yw[k], fmaf(cu2, Xw[k], fmaf(X[k], one, Y[k])));
+  } else {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) h[k] = fmaf(X[k], one, Y[k]);
+  }
+  hop_half<MU, SGN>(h, U, acc, n);
 }
 
 // ---------------------------------------------------------------- dense fifth-dimension matrices
@@ -332,6 +402,9 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
   const R pc = PRE ? (R)(a.mphi_c / a.mphi_b) : R(0);
   const R pcu = pc * ((s > 0) ? R(1) : (R)(-a.mf));
   const R pcl = pc * ((s < Ls - 1) ? R(1) : (R)(-a.mf));
+  // an opaque 1 (see hop_dir_norm)
+  float one = 1.f;
+  asm volatile("" : "+s"(one));
   // One direction is always in flight ahead of the one being computed: the
   // forward neighbour of mu uses buffer `cur`, the backward one `nxt`.  The
   // loop over mu stays rolled on purpose (unrolled, the compiler hoists all
@@ -347,15 +420,21 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
       const int d = 2 * mu + bw;
       if (kPrefetch && bw == 1 && mu < 3) cur.load(in, a.in_norm, rin + (active ? nb[d + 1] : a.zero_site), s, Ls);
       if (!kPrefetch && d > 0) cur.load(in, a.in_norm, rin + (active ? nb[d] : a.zero_site), s, Ls);
-      R v[24];
-      if (bw == 0 || !kPrefetch) cur.decode(v); else nxt.decode(v);
       const R *U = Lsite + d * 18;
       // (1 - g_mu) for the forward hop of H and the backward hop of H^+
       constexpr int sp = (DAG != 0) ? -1 : 1;
       const int sg = bw ? -sp : sp;
-#define MSPCG_DIR(M)                                                                   \
-  if (sg > 0) hop_dir<M, 1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, v, U, acc);      \
-  else hop_dir<M, -1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, v, U, acc);
+#define MSPCG_DIR(M)                                                                                        \
+  if constexpr (Traits<S>::kNorm) {                                                                         \
+    const RawSite<S> &raw = (bw == 0 || !kPrefetch) ? cur : nxt;                                           \
+    if (sg > 0) hop_dir_norm<M, 1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, one, raw, U, acc);             \
+    else hop_dir_norm<M, -1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, one, raw, U, acc);                   \
+  } else {                                                                                                  \
+    R v[24];                                                                                                \
+    if (bw == 0 || !kPrefetch) cur.decode(v); else nxt.decode(v);                                           \
+    if (sg > 0) hop_dir<M, 1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, v, U, acc);                         \
+    else hop_dir<M, -1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, v, U, acc);                               \
+  }
       switch (mu) {
         case 0: MSPCG_DIR(0) break;
         case 1: MSPCG_DIR(1) break;

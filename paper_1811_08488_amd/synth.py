@@ -117,6 +117,31 @@ def source(L, Ls: int, nrhs: int, seed: int) -> np.ndarray:
     return re_im[..., 0] + 1j * re_im[..., 1]
 
 
+def source_cb_chunks(L, Ls: int, nrhs: int, seed: int, sites_per_chunk: int = 1 << 20):
+    """The same numbers as source(), drawn in order without holding the whole
+    field: yields (rhs, cb0, even, odd) with even/odd = phi at the cb sites
+    [cb0, cb0 + n) of each parity, [n][Ls][4][3].  Chunks cover whole pairs of
+    lex sites (Lx even), so each holds the same cb range of both parities."""
+    V = int(np.prod(L))
+    Lx = L[0]
+    step = max(2 * Lx, (sites_per_chunk // (2 * Lx)) * 2 * Lx)
+    rng = np.random.default_rng(seed)
+    for r in range(nrhs):
+        for a in range(0, V, step):
+            b = min(V, a + step)
+            re_im = rng.standard_normal((b - a, Ls, 4, 3, 2)) * np.sqrt(0.5)
+            phi = re_im[..., 0] + 1j * re_im[..., 1]
+            lex = np.arange(a, b)
+            x = lex % Lx
+            rest = lex // Lx
+            y = rest % L[1]
+            rest //= L[1]
+            z = rest % L[2]
+            t = rest // L[2]
+            par = (x + y + z + t) & 1
+            yield r, a // 2, phi[par == 0], phi[par == 1]
+
+
 def cb_field(L, Ls: int, nrhs: int, seed: int) -> np.ndarray:
     """Gaussian field on one parity, [rhs][V/2][Ls][4][3] (for operator tests)."""
     V = int(np.prod(L))
