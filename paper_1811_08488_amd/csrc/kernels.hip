@@ -162,8 +162,18 @@ __device__ inline uint32_t rot_next_word(uint32_t x) { return (uint32_t)rot_next
 template <int MU, int SGN, int PRE, int XM, typename S>
 __device__ inline void hop_dir_norm(float *lds, int nthr, int tid, int s, int Ls, float cu, float cl, float one,
                                     const RawSite<S> &raw, const float *U, float acc[24]) {
+  // every direction widens its own copy of the stored words: shared by the
+  // eight direction variants, the widening would be hoisted out of them as
+  // separate conversions instead of folding into the multiply-adds
+  RawSite<S> rs = raw;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    uint32_t x = rs.word(i);
+    asm volatile("" : "+v"(x));
+    rs.set_word(i, x);
+  }
   float v[24], X[12], Y[12], h[12];
-  raw.decode_raw(v);
+  rs.decode_raw(v);
   project_parts<MU, SGN>(v, X, Y);
   float n = raw.n;
   if (PRE) {
