@@ -902,23 +902,26 @@ mspcg_status mspcg_create(mspcg_handle **hp, const mspcg_dwf *p, const double *g
     // index maps
     const int *L = p->L;
     const int Lxh = L[0] / 2;
-    // output sites of the full-lattice hop are visited in 4D tiles (extent 4
-    // where it divides the lattice, else 2) so that a tile's neighbours stay in cache
-    int tdim[4];
-    for (int mu = 0; mu < 4; ++mu) tdim[mu] = (L[mu] % 4 == 0) ? 4 : 2;
+    // output sites of the full-lattice hop are visited column by column: the
+    // lattice is cut into columns of 8x8x8 spatial sites (the full extent where
+    // 8 does not divide it) running the whole time direction, and each column
+    // is swept along t.  Consecutive workgroups (one XCD each range, see the
+    // kernels' workgroup renumbering) then need only a few neighbouring time
+    // slices of one column at a time, which stay in that XCD's L2.
+    int cdim[3];
+    for (int mu = 0; mu < 3; ++mu) cdim[mu] = (L[mu] % 8 == 0) ? 8 : L[mu];
     for (int par = 0; par < 2; ++par) {
       std::vector<int> order;
       order.reserve(h->Vh);
-      for (int bt = 0; bt < L[3]; bt += tdim[3])
-        for (int bz = 0; bz < L[2]; bz += tdim[2])
-          for (int by = 0; by < L[1]; by += tdim[1])
-            for (int bx = 0; bx < L[0]; bx += tdim[0])
-              for (int t = bt; t < bt + tdim[3]; ++t)
-                for (int z = bz; z < bz + tdim[2]; ++z)
-                  for (int y = by; y < by + tdim[1]; ++y)
-                    for (int x = bx; x < bx + tdim[0]; ++x)
-                      if (((x + y + z + t) & 1) == par) order.push_back((x + L[0] * (y + L[1] * (z + L[2] * t))) >> 1);
-      if ((int)order.size() != h->Vh) fail(MSPCG_EINVAL, "internal: tile order incomplete");
+      for (int bz = 0; bz < L[2]; bz += cdim[2])
+        for (int by = 0; by < L[1]; by += cdim[1])
+          for (int bx = 0; bx < L[0]; bx += cdim[0])
+            for (int t = 0; t < L[3]; ++t)
+              for (int z = bz; z < bz + cdim[2]; ++z)
+                for (int y = by; y < by + cdim[1]; ++y)
+                  for (int x = bx; x < bx + cdim[0]; ++x)
+                    if (((x + y + z + t) & 1) == par) order.push_back((x + L[0] * (y + L[1] * (z + L[2] * t))) >> 1);
+      if ((int)order.size() != h->Vh) fail(MSPCG_EINVAL, "internal: site order incomplete");
       upload(h->d_order[par], order, st);
     }
     for (int par = 0; par < 2; ++par) {

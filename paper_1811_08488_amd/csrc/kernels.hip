@@ -351,7 +351,7 @@ __device__ inline void wg_partial(double *ldsd, int nthr, int tid, int Ls, int n
 // for the daggered hop g5 H g5 = H^+.
 // Workgroup = (s, rhs, site) threads: threadIdx.x = s, .y = rhs, .z = site.
 // GLOBAL: the output list is the whole parity (site_cb a permutation of cb in
-// 4D-tile order); neighbour tables, outputs and the `other`/dot operands are
+// column-sweep order); neighbour tables, outputs and the `other`/dot operands are
 // indexed by cb.  Otherwise (block domains) they are indexed by the position
 // in the list, and neighbours outside the domain point at the input list's
 // zero site, which is never written.
