@@ -65,6 +65,7 @@ def build_problem(w, torch):
     h.prepare_rhs(b, fields[0], fields[1])
     torch.cuda.synchronize()
     del fields, views
+    torch.cuda.empty_cache()
     return h, A, U, eps, b
 
 
@@ -233,6 +234,8 @@ def main():
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (the method's "
               "sharding is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    # the solvers report progress every 50 outer iterations (long solves on the large lattices)
+    os.environ.setdefault("MSPCG_VERBOSE", "50")
     import torch
 
     if not torch.cuda.is_available():
@@ -260,6 +263,7 @@ def main():
         return h.cg_solve(x, b, tol=w.tol, max_iter=50000, reliable=w.reliable)
 
     for i in range(args.warmup):
+        log(f"[bench] warmup mspcg {i} (tunes launch shapes, captures the preconditioner)")
         st = mspcg_step()
         log(f"[bench] warmup mspcg {i}: {st['outer_iters']} outer, {st['seconds']:.3f}s")
     torch.cuda.synchronize()

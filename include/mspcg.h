@@ -122,7 +122,10 @@ typedef struct mspcg_handle mspcg_handle;
  * gauge field (device, FP64, physical links) is copied and repacked on
  * `stream`; the caller may free it after the call returns.
  * MSPCG_EUNSUPPORTED for b = 0 (the hop kernels factor b out of
- * M_phi = b + c P_chi). */
+ * M_phi = b + c P_chi).  Environment read here: MSPCG_AUTOTUNE=0 keeps the
+ * default workgroup shapes (no timing of candidates on first use);
+ * MSPCG_VERBOSE=n makes the solvers print their residual on stderr every n
+ * outer iterations. */
 mspcg_status mspcg_create(mspcg_handle **h, const mspcg_dwf *p, const double *gauge_dev_f64, void *stream);
 mspcg_status mspcg_destroy(mspcg_handle *h);
 

@@ -3,6 +3,7 @@
 // without the multisplitting preconditioner).
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -57,8 +58,13 @@ struct DBuf {
       fail(MSPCG_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");
     }
     bytes = n;
-    // new buffers start at zero (block lists rely on their never-written zero sites)
+    // new buffers start at zero (block lists rely on their never-written zero
+    // sites).  The clear is ordered on the null stream, which does not order
+    // against the solvers' non-blocking stream or a caller's: wait for it
+    // before any kernel can touch the buffer (allocation is first-use only,
+    // never inside a graph capture).
     HIPCHK(hipMemset(p, 0, n));
+    HIPCHK(hipDeviceSynchronize());
   }
   template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
 };
@@ -138,6 +144,7 @@ struct mspcg_handle {
   // sites per workgroup chosen by the autotuner, per kernel variant and shape
   std::map<std::vector<int>, int> tuned;
   bool autotune = true;
+  int verbose = 0;  // MSPCG_VERBOSE=n: the solvers report progress on stderr every n outer iterations
   ~mspcg_handle() {
     if (work) (void)hipStreamSynchronize(work);
     for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
@@ -575,6 +582,7 @@ void ensure_block_vecs(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs) {
       if (v->data.p) HIPCHK(hipMemset(v->data.p, 0, v->data.bytes));
       if (v->norm.p) HIPCHK(hipMemset(v->norm.p, 0, v->norm.bytes));
     }
+    HIPCHK(hipDeviceSynchronize());  // as in DBuf::ensure: the null stream orders nothing else
   }
   bg->vprec = prec;
   bg->vnrhs = nrhs;
@@ -830,6 +838,13 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
             if (active[i] && hr[i] <= tol2 * hb[i]) { active[i] = 0; changed = true; }
           if (changed) push_active();
         }
+        if (h->verbose > 0 && it % h->verbose == 0) {
+          double worst = 0;
+          for (int i = 0; i < nrhs; ++i)
+            if (hb[i] > 0) worst = std::max(worst, std::sqrt(hr[i] / hb[i]));
+          std::fprintf(stderr, "[mspcg] %s iteration %d: relative residual %.3e, %.1f s\n", pc ? "MSPCG" : "CG", it,
+                       worst, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+        }
         any = false;
         for (int a : active) any |= (a != 0);
         if (!any) break;
@@ -892,6 +907,7 @@ mspcg_status mspcg_create(mspcg_handle **hp, const mspcg_dwf *p, const double *g
     h->stream = S(stream);
     HIPCHK(hipStreamCreateWithFlags(&h->work, hipStreamNonBlocking));
     if (const char *e = std::getenv("MSPCG_AUTOTUNE")) h->autotune = std::atoi(e) != 0;
+    if (const char *e = std::getenv("MSPCG_VERBOSE")) h->verbose = std::max(0, std::atoi(e));
     h->alpha5 = p->b * (4.0 - p->M5) + 1.0;
     h->beta5 = 1.0 - p->c * (4.0 - p->M5);
     const int Ls = p->Ls;

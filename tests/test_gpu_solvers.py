@@ -164,6 +164,22 @@ def test_unsupported_blocking(S):
     assert e.value.status == M.EUNSUPPORTED
 
 
+def test_first_solve_on_fresh_handle_matches_later_solves():
+    """Buffers allocated and cleared on first use must be clear before the
+    solver's stream touches them: the first solve on a new handle gives the
+    same iterates as the following ones."""
+    require_gpu()
+    L, Ls, nblk = (8, 8, 8, 16), 8, (2, 2, 2, 2)
+    s = Setup(L, Ls, "mobius", mf=0.01, seed=12)
+    b = s.h.upload(s.rand(1, 98), 0)
+    runs = []
+    for _ in range(2):
+        fx = s.h.field(M.F64, 1, 0)
+        st = s.h.mspcg_solve(fx, b, nblk, 4, M.F16, tol=1e-10)
+        runs.append((st["outer_iters"], s.h.download(fx)))
+    assert runs[0][0] == runs[1][0] and np.array_equal(runs[0][1], runs[1][1])
+
+
 def test_graph_replay_matches_eager(S):
     """The captured preconditioner (replayed every outer iteration, with the
     solver's own eager kernels and host synchronisations between replays) gives
