@@ -1,6 +1,7 @@
 // C-ABI entry points: handle, geometry tables, operators, the batched block
 // CG preconditioner and the two FP64 outer solvers (Algorithm 1 with and
 // without the multisplitting preconditioner).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -176,7 +177,7 @@ hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 // sites per workgroup: the largest power of two with <= 256 threads (>= 1)
 int pick_nsite(int nrhs, int Ls) {
   int n = 1;
-  while (n * 2 <= kPad && n * 2 * nrhs * Ls <= 256) n *= 2;
+  while (n * 2 <= kPad && hop_threads(Ls, nrhs, n * 2) <= 256) n *= 2;
   return n;
 }
 
@@ -244,7 +245,8 @@ void check_field(mspcg_handle *h, const mspcg_field *f, const char *name) {
   if (f->parity != 0 && f->parity != 1) fail(MSPCG_EINVAL, std::string(name) + ": parity must be 0 or 1");
   if (f->prec < MSPCG_F64 || f->prec > MSPCG_BF16) fail(MSPCG_EINVAL, std::string(name) + ": unknown precision");
   if (prec_norm(f->prec) && !f->norm) fail(MSPCG_EINVAL, std::string(name) + ": F16/BF16 field without norm array");
-  if (f->nrhs * h->par.Ls > 256) fail(MSPCG_EUNSUPPORTED, std::string(name) + ": nrhs * Ls above 256");
+  if (hop_threads(h->par.Ls, f->nrhs, 1) > 256)
+    fail(MSPCG_EUNSUPPORTED, std::string(name) + ": one site's nrhs x Ls lanes exceed a 256-thread workgroup");
 }
 
 Vec vec_of(mspcg_handle *h, const mspcg_field *f) {
@@ -295,16 +297,33 @@ int run_hop(mspcg_handle *h, int list_kind, int prec, int dag, int pre, int epi,
   if (it != h->tuned.end()) {
     n = it->second;
   } else {
-    const int n0 = pick_nsite(a.nrhs, a.Ls);
+    // Candidates: powers of two up to kPad (a per-block reduction, block-list
+    // hops with a fused dot product, needs workgroups that never straddle the
+    // 64-site block padding), and otherwise also the site counts that fill
+    // whole waves when Ls does not divide 64 (multiples of 5 sites for Ls = 12).
+    std::vector<int> cands;
+    for (int c = 1; c <= kPad; c *= 2) cands.push_back(c);
+    const int G = hop_groups_per_wave(a.Ls);
+    if (G > 0 && (global || !dot))
+      for (int w = 1; w <= 4; ++w)
+        if ((G * w) % a.nrhs == 0 && std::find(cands.begin(), cands.end(), G * w / a.nrhs) == cands.end())
+          cands.push_back(G * w / a.nrhs);
+    int n0 = pick_nsite(a.nrhs, a.Ls);
+    if (G > 0 && (global || !dot))  // default: the fullest workgroup of whole waves
+      for (int w = 4; w >= 1; --w)
+        if ((G * w) % a.nrhs == 0) {
+          n0 = G * w / a.nrhs;
+          break;
+        }
     n = n0;
     if (h->autotune) {
       hipEvent_t e0, e1;
       HIPCHK(hipEventCreate(&e0));
       HIPCHK(hipEventCreate(&e1));
       float best = 0;
-      for (int c = 1; c <= kPad; c *= 2) {
-        const int thr = c * a.nrhs * a.Ls;
-        if (thr > 256 || (thr < 64 && 2 * thr <= 256 && c < kPad)) continue;
+      for (int c : cands) {
+        const int thr = hop_threads(a.Ls, a.nrhs, c);
+        if (thr > 256 || (thr < 64 && hop_threads(a.Ls, a.nrhs, 2 * c) <= 256 && c < kPad)) continue;
         a.nsite_wg = c;
         if (launch_hop(prec, dag, pre, epi, dot, global, a, st) != hipSuccess) {
           (void)hipGetLastError();

@@ -50,9 +50,26 @@ __device__ inline double perm(int addr, double x) {
   return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_ds_bpermute(addr, t.x), __builtin_amdgcn_ds_bpermute(addr, t.y)));
 }
 
-// Exchange modes, fixed per launch from Ls (the kernels are instantiated per mode).
+// Exchange modes, fixed per launch from Ls (the kernels are instantiated per
+// mode), and the lane layout that goes with them.  With DPP and ds_bpermute
+// exchanges every 64-lane wave holds G = 64/Ls whole (site, rhs) groups of Ls
+// lanes; the last 64 - G*Ls lanes of a wave are idle (4 of 64 for Ls = 12).
+// Where that would idle more than 8 lanes (Ls = 24: 16) the groups are packed
+// densely instead and exchange through LDS with barriers.
 constexpr int kXDpp16 = 0, kXPerm = 1, kXLds = 2;
-static inline int xmode(int Ls) { return Ls == 16 ? kXDpp16 : (64 % Ls == 0 ? kXPerm : kXLds); }
+static inline int xmode(int Ls) {
+  if (Ls == 16) return kXDpp16;
+  return (Ls <= 64 && 64 - (64 / Ls) * Ls <= 8) ? kXPerm : kXLds;
+}
+// groups per wave of the layout (0: dense packing)
+__host__ __device__ inline int groups_per_wave(int xm, int Ls) { return xm == kXLds ? 0 : 64 / Ls; }
+// thread index of lane t of group g
+__device__ inline int group_tid(int G, int Ls, int g, int t) { return G ? (g / G) * 64 + (g % G) * Ls + t : g * Ls + t; }
+// threads of a workgroup of `groups` groups
+static inline int layout_threads(int xm, int Ls, int groups) {
+  const int G = groups_per_wave(xm, Ls);
+  return G ? 64 * ((groups + G - 1) / G) : groups * Ls;
+}
 
 // v <- a v + b P_chi v (DAG = 0) or a v + b P_chi^+ v (DAG = 1) on the Ls column
 // held one s per lane.  P_chi = P- S+ + P+ S-: chirality + (reals 0..11) takes
@@ -250,11 +267,11 @@ __device__ inline f64x4 mfma16x16x4(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// lds: [24][nthr] structure of arrays; X: [2][Ls][Ls] (LDS copy).  Lane l of a
-// wave supplies A[l%16][l/16] and B[l/16][l%16] and receives four entries of
-// column l%16 of D.
+// lds: [24][nthr] structure of arrays; X: [2][Ls][Ls] (LDS copy); G: the lane
+// layout (groups per wave, 0: dense).  Lane l of a wave supplies A[l%16][l/16]
+// and B[l/16][l%16] and receives four entries of column l%16 of D.
 template <typename R>
-__device__ inline void dense_chiral(R *lds, const R *X, int nthr, int tid, int s, int Ls, int ngroups, R scale,
+__device__ inline void dense_chiral(R *lds, const R *X, int nthr, int tid, int s, int Ls, int ngroups, int G, R scale,
                                    R v[24]) {
   __syncthreads();
 #pragma unroll
@@ -276,7 +293,7 @@ __device__ inline void dense_chiral(R *lds, const R *X, int nthr, int tid, int s
       T4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
       for (int k0 = 0; k0 < Ls; k0 += 4) {
         const int t = k0 + kq;
-        const R b = colok ? lds[comp * nthr + g * Ls + t] : R(0);
+        const R b = colok ? lds[comp * nthr + group_tid(G, Ls, g, t)] : R(0);
         const R a0 = (row < Ls) ? Xc[row * Ls + t] : R(0);
         c0 = mfma16x16x4(a0, b, c0);
         if (Ls > 16) {
@@ -290,8 +307,8 @@ __device__ inline void dense_chiral(R *lds, const R *X, int nthr, int tid, int s
           // output rows of the 16x16x4 MFMA: FP32 puts rows 4(l/16)+i in lane l's
           // four results, FP64 rows 4i + l/16
           const int m = (sizeof(R) == 8) ? 4 * i + kq : 4 * kq + i;
-          if (m < Ls) lds[comp * nthr + g * Ls + m] = scale * c0[i];
-          if (Ls > 16 && 16 + m < Ls) lds[comp * nthr + g * Ls + 16 + m] = scale * c1[i];
+          if (m < Ls) lds[comp * nthr + group_tid(G, Ls, g, m)] = scale * c0[i];
+          if (Ls > 16 && 16 + m < Ls) lds[comp * nthr + group_tid(G, Ls, g, 16 + m)] = scale * c1[i];
         }
       }
     }
@@ -326,7 +343,7 @@ __device__ inline int xcd_tile(int b, int n) {
 
 // Workgroup sum of `val` per right-hand side into partial[tile * nrhs + r]
 // (fixed order: deterministic).  Uses the LDS region as doubles.
-__device__ inline void wg_partial(double *ldsd, int nthr, int tid, int Ls, int nrhs, int nsite_wg, double val,
+__device__ inline void wg_partial(double *ldsd, int nthr, int tid, int Ls, int nrhs, int nsite_wg, int G, double val,
                                   double *partial, int tile) {
   __syncthreads();
   ldsd[tid] = val;
@@ -334,7 +351,7 @@ __device__ inline void wg_partial(double *ldsd, int nthr, int tid, int Ls, int n
   const int ngroups = nsite_wg * nrhs;
   if (tid < ngroups) {
     double acc = 0;
-    for (int s = 0; s < Ls; ++s) acc += ldsd[tid * Ls + s];
+    for (int s = 0; s < Ls; ++s) acc += ldsd[group_tid(G, Ls, tid, s)];
     ldsd[nthr + tid] = acc;
   }
   __syncthreads();
@@ -365,16 +382,31 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
   using R = typename Traits<S>::R;
   extern __shared__ __align__(16) unsigned char smem[];
   const int Ls = a.Ls, nrhs = a.nrhs, nsw = a.nsite_wg;
-  const int s = threadIdx.x, r = threadIdx.y, sl = threadIdx.z;
-  const int nthr = Ls * nrhs * nsw;
-  const int tid = s + Ls * (r + nrhs * sl);
+  // lane -> (s, group = rhs + nrhs * site-in-workgroup); see groups_per_wave
+  const int G = groups_per_wave(XM, Ls);
+  const int nthr = blockDim.x * blockDim.y * blockDim.z;
+  int s, r, sl, tid;
+  bool lane_ok = true;
+  if (XM == kXLds) {
+    s = threadIdx.x, r = threadIdx.y, sl = threadIdx.z;
+    tid = s + Ls * (r + nrhs * sl);
+  } else {
+    tid = threadIdx.x;
+    const int lane = tid & 63, gi = lane / Ls;
+    s = lane - gi * Ls;
+    int g = (tid >> 6) * G + gi;
+    lane_ok = gi < G && g < nrhs * nsw;  // idle lanes compute on the zero site and store nothing
+    if (!lane_ok) g = 0;
+    r = g % nrhs;
+    sl = g / nrhs;
+  }
   R *Lk = reinterpret_cast<R *>(smem);  // [nsite_wg][8][18] links of this workgroup's sites
   R *Xl = Lk + nsw * 144;               // [2][Ls][Ls] dense epilogue matrix
   R *lds = Xl + (EPI == EPI_DENSE ? 2 * Ls * Ls : 0);  // [24][nthr] exchanges (LDS mode, dense epilogue)
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int site = tile * nsw + sl;
   const int cbr = (site < a.nsites) ? a.site_cb[site] : -1;
-  const bool active = cbr >= 0;
+  const bool active = lane_ok && cbr >= 0;
   const int cb = active ? cbr : 0;
   const int self = GLOBAL ? cb : site;  // index of this site in tables and outputs
 
@@ -457,7 +489,7 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
 
   const R scale = (R)(PRE ? a.scale * a.mphi_b : a.scale);
   if (EPI == EPI_DENSE) {
-    dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * nsw, scale, acc);
+    dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * nsw, G, scale, acc);
   } else if (EPI == EPI_MPHIDAG || EPI == EPI_M5DAG_MPHIDAG) {
     pchi_comb<1, XM, R>(lds, nthr, tid, s, Ls, (R)a.mphi_b, (R)a.mphi_c, (R)a.mf, acc);
 #pragma unroll
@@ -489,7 +521,7 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
       for (int k = 0; k < 24; ++k) t += w[k] * acc[k];
       val = (double)t;
     }
-    wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, nrhs, nsw, val, a.partial, tile);
+    wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, nrhs, nsw, G, val, a.partial, tile);
   }
 }
 
@@ -505,11 +537,11 @@ static size_t hop_lds_bytes(const HopArgs &a, int nthr, int epi, int dot, int xm
 
 template <typename S, int DAG, int PRE, int EPI, int DOT, int GLOBAL>
 static hipError_t launch_hop_t(const HopArgs &a, hipStream_t st) {
-  const int nthr = a.nsite_wg * a.nrhs * a.Ls;
-  const int grid = (a.nsites + a.nsite_wg - 1) / a.nsite_wg;
-  if (nthr < 1 || nthr > 256 || grid < 1) return hipErrorInvalidValue;
-  const dim3 blk(a.Ls, a.nrhs, a.nsite_wg);
   const int xm = xmode(a.Ls);
+  const int nthr = layout_threads(xm, a.Ls, a.nsite_wg * a.nrhs);
+  const int grid = (a.nsites + a.nsite_wg - 1) / a.nsite_wg;
+  if (a.nsite_wg < 1 || nthr > 256 || grid < 1) return hipErrorInvalidValue;
+  const dim3 blk = (xm == kXLds) ? dim3(a.Ls, a.nrhs, a.nsite_wg) : dim3(nthr);
   const size_t lds = hop_lds_bytes<S>(a, nthr, EPI, DOT, xm);
   switch (xm) {
     case kXDpp16: hipLaunchKernelGGL((hop_kernel<S, DAG, PRE, EPI, DOT, GLOBAL, kXDpp16>), dim3(grid), blk, lds, st, a); break;
@@ -518,6 +550,9 @@ static hipError_t launch_hop_t(const HopArgs &a, hipStream_t st) {
   }
   return hipGetLastError();
 }
+
+int hop_threads(int Ls, int nrhs, int nsite_wg) { return layout_threads(xmode(Ls), Ls, nrhs * nsite_wg); }
+int hop_groups_per_wave(int Ls) { return groups_per_wave(xmode(Ls), Ls); }
 
 template <typename S>
 static hipError_t dispatch_hop(int dagger, int pre, int epi, int dot, int global, const HopArgs &a, hipStream_t st) {
@@ -557,13 +592,27 @@ __global__ void __launch_bounds__(256) op5_kernel(const Op5Args a) {
   using R = typename Traits<S>::R;
   extern __shared__ __align__(16) unsigned char smem[];
   const int Ls = a.Ls, nrhs = a.nrhs;
-  const int s = threadIdx.x, r = threadIdx.y, sl = threadIdx.z;
-  const int nthr = Ls * nrhs * a.nsite_wg;
-  const int tid = s + Ls * (r + nrhs * sl);
+  const int G = groups_per_wave(XM, Ls);  // lane layout as in hop_kernel
+  const int nthr = blockDim.x * blockDim.y * blockDim.z;
+  int s, r, sl, tid;
+  bool lane_ok = true;
+  if (XM == kXLds) {
+    s = threadIdx.x, r = threadIdx.y, sl = threadIdx.z;
+    tid = s + Ls * (r + nrhs * sl);
+  } else {
+    tid = threadIdx.x;
+    const int lane = tid & 63, gi = lane / Ls;
+    s = lane - gi * Ls;
+    int g = (tid >> 6) * G + gi;
+    lane_ok = gi < G && g < nrhs * a.nsite_wg;
+    if (!lane_ok) g = 0;
+    r = g % nrhs;
+    sl = g / nrhs;
+  }
   R *lds = reinterpret_cast<R *>(smem);
   R *Xl = lds + 24 * nthr;
   const int site = blockIdx.x * a.nsite_wg + sl;
-  const bool active = site < a.nsites;
+  const bool active = lane_ok && site < a.nsites;
   if (a.dense) {
     const R *Xg = reinterpret_cast<const R *>(a.mat);
     for (int i = tid; i < 2 * Ls * Ls; i += nthr) Xl[i] = Xg[i];
@@ -572,7 +621,7 @@ __global__ void __launch_bounds__(256) op5_kernel(const Op5Args a) {
   const size_t idx = (size_t)r * a.stride + (active ? site : 0);
   load24<R>(reinterpret_cast<const S *>(a.in), a.in_norm, idx, s, Ls, v);
   if (a.dense)
-    dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * a.nsite_wg, R(1), v);
+    dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * a.nsite_wg, G, R(1), v);
   else if (a.dag)
     pchi_comb<1, XM, R>(lds, nthr, tid, s, Ls, (R)a.a, (R)a.b, (R)a.mf, v);
   else
@@ -590,12 +639,13 @@ static void launch_op5_t(const Op5Args &a, dim3 grid, dim3 blk, size_t lds, hipS
 }
 
 hipError_t launch_op5(int prec, const Op5Args &a, hipStream_t st) {
-  const int nthr = a.nsite_wg * a.nrhs * a.Ls;
+  const int xm = xmode(a.Ls);
+  const int nthr = layout_threads(xm, a.Ls, a.nsite_wg * a.nrhs);
   const int grid = (a.nsites + a.nsite_wg - 1) / a.nsite_wg;
-  if (nthr < 1 || nthr > 256 || grid < 1) return hipErrorInvalidValue;
+  if (a.nsite_wg < 1 || nthr > 256 || grid < 1) return hipErrorInvalidValue;
   const size_t rsz = (prec == MSPCG_F64) ? 8 : 4;
   const size_t lds = (24 * (size_t)nthr + 2 * (size_t)a.Ls * a.Ls) * rsz;
-  const dim3 blk(a.Ls, a.nrhs, a.nsite_wg);
+  const dim3 blk = (xm == kXLds) ? dim3(a.Ls, a.nrhs, a.nsite_wg) : dim3(nthr);
   switch (prec) {
     case MSPCG_F64: launch_op5_t<double>(a, dim3(grid), blk, lds, st); break;
     case MSPCG_F32: launch_op5_t<float>(a, dim3(grid), blk, lds, st); break;
@@ -817,7 +867,7 @@ __global__ void __launch_bounds__(256) k_block_gather(const BlockArgs b, Vec xs,
     for (int k = 0; k < 24; ++k) acc += v[k] * v[k];
     val = (double)acc;
   }
-  wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, b.nrhs, b.nsite_wg, val, partial, blockIdx.x);
+  wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, b.nrhs, b.nsite_wg, 0, val, partial, blockIdx.x);
 }
 
 template <typename S>
@@ -846,7 +896,7 @@ __global__ void __launch_bounds__(256) k_block_scatter(const BlockArgs b, double
       for (int k = 0; k < 24; ++k) val += z[k] * t[k];
     }
   }
-  wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, b.nrhs, b.nsite_wg, val, partial, blockIdx.x);
+  wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, b.nrhs, b.nsite_wg, 0, val, partial, blockIdx.x);
 }
 
 template <typename S>
@@ -881,7 +931,7 @@ __global__ void __launch_bounds__(256) k_block_update_xr(const BlockArgs b, Vec 
     for (int k = 0; k < 24; ++k) acc += rr[k] * rr[k];
     val = (double)acc;
   }
-  wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, b.nrhs, b.nsite_wg, val, partial, blockIdx.x);
+  wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, b.nrhs, b.nsite_wg, 0, val, partial, blockIdx.x);
 }
 
 template <typename S>
