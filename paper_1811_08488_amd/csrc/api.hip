@@ -111,7 +111,16 @@ struct BlockGeom {
   DBuf partial, scal, rrbuf;
 };
 
-constexpr int kPad = 64;  // block lists are padded to multiples of this many sites
+constexpr int kPad = 64;  // zero sites after a block list; block lists are padded to multiples of block_align
+
+// Block lists are padded to a multiple of this many sites, so that workgroups
+// of the block kernels (any power of two up to 64 sites) and the whole-wave
+// site counts of the hop layout (G sites of one right-hand side fill a wave)
+// never straddle two blocks: 64, or 64 G when G is not a power of two.
+int block_align(int Ls) {
+  const int G = hop_groups_per_wave(Ls);
+  return (G > 0 && (G & (G - 1)) != 0) ? kPad * G : kPad;
+}
 
 // A dense fifth-dimension operator [2][Ls][Ls] in FP64 and FP32 (the compute
 // types of the kernels).
@@ -297,21 +306,25 @@ int run_hop(mspcg_handle *h, int list_kind, int prec, int dag, int pre, int epi,
   if (it != h->tuned.end()) {
     n = it->second;
   } else {
-    // Candidates: powers of two up to kPad (a per-block reduction, block-list
-    // hops with a fused dot product, needs workgroups that never straddle the
-    // 64-site block padding), and otherwise also the site counts that fill
-    // whole waves when Ls does not divide 64 (multiples of 5 sites for Ls = 12).
+    // Candidates: powers of two up to kPad, and the site counts that fill
+    // whole waves when Ls does not divide 64 (multiples of 5 sites for
+    // Ls = 12).  A block-list hop with a fused dot product reduces per block,
+    // so its workgroups must not straddle blocks: only divisors of the block
+    // alignment.
+    const int G = hop_groups_per_wave(a.Ls);
+    const int al = block_align(a.Ls);
+    auto allowed = [&](int c) { return global || !dot || al % c == 0; };
     std::vector<int> cands;
     for (int c = 1; c <= kPad; c *= 2) cands.push_back(c);
-    const int G = hop_groups_per_wave(a.Ls);
-    if (G > 0 && (global || !dot))
+    if (G > 0)
       for (int w = 1; w <= 4; ++w)
-        if ((G * w) % a.nrhs == 0 && std::find(cands.begin(), cands.end(), G * w / a.nrhs) == cands.end())
+        if ((G * w) % a.nrhs == 0 && allowed(G * w / a.nrhs) &&
+            std::find(cands.begin(), cands.end(), G * w / a.nrhs) == cands.end())
           cands.push_back(G * w / a.nrhs);
     int n0 = pick_nsite(a.nrhs, a.Ls);
-    if (G > 0 && (global || !dot))  // default: the fullest workgroup of whole waves
+    if (G > 0)  // default: the fullest workgroup of whole waves
       for (int w = 4; w >= 1; --w)
-        if ((G * w) % a.nrhs == 0) {
+        if ((G * w) % a.nrhs == 0 && allowed(G * w / a.nrhs) && hop_threads(a.Ls, a.nrhs, G * w / a.nrhs) <= 256) {
           n0 = G * w / a.nrhs;
           break;
         }
@@ -465,8 +478,8 @@ BlockGeom *get_blocks(mspcg_handle *h, const int nblk[4], int no_snake, hipStrea
           }
     const int be0 = bg->be_off.back(), o10 = bg->o1_off.back(), e20 = bg->e2_off.back();
     const int nbe = (int)loc_be.size(), no1 = (int)loc_o1.size(), ne2 = (int)loc_e2.size();
-    const int pbe = (nbe + kPad - 1) / kPad * kPad, po1 = (no1 + kPad - 1) / kPad * kPad,
-              pe2 = (ne2 + kPad - 1) / kPad * kPad;
+    const int al = block_align(h->par.Ls);
+    const int pbe = (nbe + al - 1) / al * al, po1 = (no1 + al - 1) / al * al, pe2 = (ne2 + al - 1) / al * al;
     for (int i = 0; i < no1; ++i) o1_of_lex[loc_o1[i]] = o10 + i;
     for (int i = 0; i < ne2; ++i) e2_of_lex[loc_e2[i]] = e20 + i;
     std::vector<int> be_of_e2(ne2, -1);

@@ -109,7 +109,7 @@ struct BlockArgs {
   const int *be_cb;   // [nsites]
   const int *be_blk;  // [nsites] block of the site (-1: padding)
   int nblocks;
-  const int *be_off;  // [nblocks+1] padded offsets (multiples of 64)
+  const int *be_off;  // [nblocks+1] padded offsets (multiples of the block alignment, itself a multiple of 64)
 };
 // r_s = p_s = scale * r(cb), x_s = 0; partial |r_s|^2 per workgroup.  scale = sqrt(n_total/rr[rhs]).
 hipError_t block_gather(int prec, const BlockArgs &b, const Vec &xs, const Vec &rs, const Vec &ps, const Vec &rglob,

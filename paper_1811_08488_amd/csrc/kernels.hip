@@ -272,8 +272,8 @@ __device__ inline f64x4 mfma16x16x4(double a, double b, f64x4 c) {
 // and B[l/16][l%16] and receives four entries of column l%16 of D.
 template <typename R>
 __device__ inline void dense_chiral(R *lds, const R *X, int nthr, int tid, int s, int Ls, int ngroups, int G, R scale,
-                                   R v[24]) {
-  __syncthreads();
+                                   R v[24], bool lds_in_use) {
+  if (lds_in_use) __syncthreads();  // earlier exchanges through the same LDS words
 #pragma unroll
   for (int k = 0; k < 24; ++k) lds[k * nthr + tid] = v[k];
   __syncthreads();
@@ -489,7 +489,7 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
 
   const R scale = (R)(PRE ? a.scale * a.mphi_b : a.scale);
   if (EPI == EPI_DENSE) {
-    dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * nsw, G, scale, acc);
+    dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * nsw, G, scale, acc, XM == kXLds);
   } else if (EPI == EPI_MPHIDAG || EPI == EPI_M5DAG_MPHIDAG) {
     pchi_comb<1, XM, R>(lds, nthr, tid, s, Ls, (R)a.mphi_b, (R)a.mphi_c, (R)a.mf, acc);
 #pragma unroll
@@ -621,7 +621,7 @@ __global__ void __launch_bounds__(256) op5_kernel(const Op5Args a) {
   const size_t idx = (size_t)r * a.stride + (active ? site : 0);
   load24<R>(reinterpret_cast<const S *>(a.in), a.in_norm, idx, s, Ls, v);
   if (a.dense)
-    dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * a.nsite_wg, G, R(1), v);
+    dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * a.nsite_wg, G, R(1), v, false);
   else if (a.dag)
     pchi_comb<1, XM, R>(lds, nthr, tid, s, Ls, (R)a.a, (R)a.b, (R)a.mf, v);
   else
