@@ -118,7 +118,7 @@ constexpr int kPad = 64;  // zero sites after a block list; block lists are padd
 // site counts of the hop layout (G sites of one right-hand side fill a wave)
 // never straddle two blocks: 64, or 64 G when G is not a power of two.
 int block_align(int Ls) {
-  const int G = hop_groups_per_wave(Ls);
+  const int G = hop_groups_per_wave(Ls, 1);  // the layout of one right-hand side (a multiple for the others)
   return (G > 0 && (G & (G - 1)) != 0) ? kPad * G : kPad;
 }
 
@@ -311,7 +311,7 @@ int run_hop(mspcg_handle *h, int list_kind, int prec, int dag, int pre, int epi,
     // Ls = 12).  A block-list hop with a fused dot product reduces per block,
     // so its workgroups must not straddle blocks: only divisors of the block
     // alignment.
-    const int G = hop_groups_per_wave(a.Ls);
+    const int G = hop_groups_per_wave(a.Ls, a.nrhs);
     const int al = block_align(a.Ls);
     auto allowed = [&](int c) { return global || !dot || al % c == 0; };
     std::vector<int> cands;

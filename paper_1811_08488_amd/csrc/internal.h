@@ -58,7 +58,7 @@ struct HopArgs {
 // right-hand sides (the lane layout depends on Ls); at most 256.
 int hop_threads(int Ls, int nrhs, int nsite_wg);
 // (site, rhs) groups per 64-lane wave of that layout (0: densely packed lanes)
-int hop_groups_per_wave(int Ls);
+int hop_groups_per_wave(int Ls, int nrhs);
 
 // Launch the hop kernel for storage `prec`; returns hipSuccess or the launch error.
 hipError_t launch_hop(int prec, int dagger, int pre_mphi, int epi, int dot, int global, const HopArgs &a,

@@ -50,16 +50,24 @@ __device__ inline double perm(int addr, double x) {
   return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_ds_bpermute(addr, t.x), __builtin_amdgcn_ds_bpermute(addr, t.y)));
 }
 
-// Exchange modes, fixed per launch from Ls (the kernels are instantiated per
-// mode), and the lane layout that goes with them.  With DPP and ds_bpermute
-// exchanges every 64-lane wave holds G = 64/Ls whole (site, rhs) groups of Ls
-// lanes; the last 64 - G*Ls lanes of a wave are idle (4 of 64 for Ls = 12).
-// Where that would idle more than 8 lanes (Ls = 24: 16) the groups are packed
-// densely instead and exchange through LDS with barriers.
+// Exchange modes, fixed per launch from Ls and nrhs (the kernels are
+// instantiated per mode), and the lane layout that goes with them.  With DPP
+// and ds_bpermute exchanges every 64-lane wave holds G = 64/Ls whole (site,
+// rhs) groups of Ls lanes; the last 64 - G*Ls lanes of a wave are idle (4 of
+// 64 for Ls = 12).  That layout is used where at most 8 lanes per wave idle
+// and some workgroup of whole sites (all nrhs groups of a site together)
+// fills whole waves; otherwise (Ls = 24; Ls = 12 with 8 right-hand sides) the
+// groups are packed densely and exchange through LDS with barriers.
 constexpr int kXDpp16 = 0, kXPerm = 1, kXLds = 2;
-static inline int xmode(int Ls) {
+static inline int xmode(int Ls, int nrhs) {
   if (Ls == 16) return kXDpp16;
-  return (Ls <= 64 && 64 - (64 / Ls) * Ls <= 8) ? kXPerm : kXLds;
+  if (Ls > 64) return kXLds;
+  const int G = 64 / Ls;
+  if (64 % Ls == 0) return kXPerm;
+  if (64 - G * Ls > 8) return kXLds;
+  for (int c = 1; nrhs * c <= 4 * G; ++c)
+    if ((nrhs * c) % G == 0) return kXPerm;
+  return kXLds;
 }
 // groups per wave of the layout (0: dense packing)
 __host__ __device__ inline int groups_per_wave(int xm, int Ls) { return xm == kXLds ? 0 : 64 / Ls; }
@@ -537,7 +545,7 @@ static size_t hop_lds_bytes(const HopArgs &a, int nthr, int epi, int dot, int xm
 
 template <typename S, int DAG, int PRE, int EPI, int DOT, int GLOBAL>
 static hipError_t launch_hop_t(const HopArgs &a, hipStream_t st) {
-  const int xm = xmode(a.Ls);
+  const int xm = xmode(a.Ls, a.nrhs);
   const int nthr = layout_threads(xm, a.Ls, a.nsite_wg * a.nrhs);
   const int grid = (a.nsites + a.nsite_wg - 1) / a.nsite_wg;
   if (a.nsite_wg < 1 || nthr > 256 || grid < 1) return hipErrorInvalidValue;
@@ -551,8 +559,8 @@ static hipError_t launch_hop_t(const HopArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-int hop_threads(int Ls, int nrhs, int nsite_wg) { return layout_threads(xmode(Ls), Ls, nrhs * nsite_wg); }
-int hop_groups_per_wave(int Ls) { return groups_per_wave(xmode(Ls), Ls); }
+int hop_threads(int Ls, int nrhs, int nsite_wg) { return layout_threads(xmode(Ls, nrhs), Ls, nrhs * nsite_wg); }
+int hop_groups_per_wave(int Ls, int nrhs) { return groups_per_wave(xmode(Ls, nrhs), Ls); }
 
 template <typename S>
 static hipError_t dispatch_hop(int dagger, int pre, int epi, int dot, int global, const HopArgs &a, hipStream_t st) {
@@ -631,7 +639,7 @@ __global__ void __launch_bounds__(256) op5_kernel(const Op5Args a) {
 
 template <typename S>
 static void launch_op5_t(const Op5Args &a, dim3 grid, dim3 blk, size_t lds, hipStream_t st) {
-  switch (xmode(a.Ls)) {
+  switch (xmode(a.Ls, a.nrhs)) {
     case kXDpp16: hipLaunchKernelGGL((op5_kernel<S, kXDpp16>), grid, blk, lds, st, a); break;
     case kXPerm: hipLaunchKernelGGL((op5_kernel<S, kXPerm>), grid, blk, lds, st, a); break;
     default: hipLaunchKernelGGL((op5_kernel<S, kXLds>), grid, blk, lds, st, a); break;
@@ -639,7 +647,7 @@ static void launch_op5_t(const Op5Args &a, dim3 grid, dim3 blk, size_t lds, hipS
 }
 
 hipError_t launch_op5(int prec, const Op5Args &a, hipStream_t st) {
-  const int xm = xmode(a.Ls);
+  const int xm = xmode(a.Ls, a.nrhs);
   const int nthr = layout_threads(xm, a.Ls, a.nsite_wg * a.nrhs);
   const int grid = (a.nsites + a.nsite_wg - 1) / a.nsite_wg;
   if (a.nsite_wg < 1 || nthr > 256 || grid < 1) return hipErrorInvalidValue;
