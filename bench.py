@@ -94,6 +94,32 @@ def time_dslash(h, A, w, prec, reps=50, warm=5):
     return {"ms": ms, "bytes": bytes_, "gbs": bytes_ / (ms * 1e-3) / 1e9}
 
 
+def time_m5inv(h, A, w, prec, reps=50, warm=5):
+    """Average duration of one m5inv launch (HIP events on the launch stream)."""
+    import torch
+
+    stream = torch.cuda.Stream()
+    fin = h.field(prec, w.nrhs, 1)
+    fout = h.field(prec, w.nrhs, 1)
+    with torch.cuda.stream(stream):
+        src = h.upload(synth.cb_field(w.L, w.Ls, w.nrhs, 98), 1, M.F64)
+        h.convert(fin, src, stream=stream)
+        for _ in range(warm):
+            h.m5inv(fout, fin, 0, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            h.m5inv(fout, fin, 0, stream=stream)
+        e1.record(stream)
+        stream.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    w_, n = BYTES[prec]
+    bytes_ = 2 * (24 * w_ + n) * (A.V // 2) * w.Ls * w.nrhs
+    flops = 2 * 2 * 12 * w.Ls * w.Ls * (A.V // 2) * w.nrhs  # two chiralities, 12 columns each, Ls x Ls multiply-adds
+    return {"us": ms * 1e3, "GB/s": bytes_ / (ms * 1e-3) / 1e9, "frac_hbm": bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "TFLOP/s": flops / (ms * 1e-3) / 1e12}
+
+
 def kernel_source_hash():
     """SHA-256 of the HIP sources the hop kernel is compiled from."""
     import hashlib
@@ -178,6 +204,11 @@ def kernels_only(w, torch):
         h.convert(fin, src)
         for _ in range(10):
             h.dslash_eo(fout, fin, 0)
+    for p in (M.F64, M.F32):  # M_5^{-1}: the dense fifth-dimension contraction on the matrix cores
+        fin, fout = h.field(p, w.nrhs, 1), h.field(p, w.nrhs, 1)
+        h.convert(fin, src)
+        for _ in range(10):
+            h.m5inv(fout, fin, 0)
     dst = h.field(M.F64, w.nrhs, 1)
     for _ in range(10):
         h.convert(dst, src)
@@ -289,6 +320,9 @@ def main():
     dsl = {p: time_dslash(h, A, w, PREC[p]) for p in ("f64", "f32", "f16")}
     for p, d in dsl.items():
         log(f"[bench] dslash_eo {p}: {d['ms'] * 1e3:.1f} us, {d['gbs']:.0f} GB/s")
+    m5 = {p: time_m5inv(h, A, w, PREC[p]) for p in ("f64", "f32")}
+    for p, d in m5.items():
+        log(f"[bench] m5inv {p}: {d['us']:.1f} us, {d['GB/s']:.0f} GB/s")
     main_k = dsl["f64"]
     out = {
         "metric": METRIC,
@@ -315,6 +349,7 @@ def main():
         "mspcg_speedup_vs_cg": None if t_cg is None else t_cg / t_ms,
         "dslash_eo": {p: {"us": d["ms"] * 1e3, "GB/s": d["gbs"], "frac_hbm": d["gbs"] / HBM_PEAK_GBS}
                       for p, d in dsl.items()},
+        "m5inv": m5,
         "roofline": {"bound": "hbm", "achieved": main_k["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": main_k["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(w.name, "f64"),
                      "algorithmic_bytes": main_k["bytes"], "avg_launch_us": main_k["ms"] * 1e3,
