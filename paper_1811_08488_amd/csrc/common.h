@@ -1,5 +1,5 @@
 // Device-side building blocks shared by the HIP kernels: storage traits for
-// the four field formats, 24-real site loads/stores, link loads and the
+// the four field formats, 24-real site loads/stores, link widening and the
 // chiral-basis spin projection of the Wilson hop.
 #pragma once
 
@@ -217,19 +217,6 @@ template <> struct RawSite<_Float16> {
 #pragma unroll
     for (int k = 0; k < 3; ++k) c[k] = *reinterpret_cast<const uint4 *>(base + chunk_index<_Float16>(site4, s, Ls, k));
   }
-  template <typename R> __device__ void decode(R v[24]) const {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const uint32_t w[4] = {c[k].x, c[k].y, c[k].z, c[k].w};
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        union { uint32_t u; _Float16 h[2]; } t;
-        t.u = w[j];
-        v[8 * k + 2 * j] = (R)((float)t.h[0] * n);
-        v[8 * k + 2 * j + 1] = (R)((float)t.h[1] * n);
-      }
-    }
-  }
 };
 template <> struct RawSite<bf16> {
   uint4 c[3];
@@ -250,17 +237,6 @@ template <> struct RawSite<bf16> {
     n = norm[site4 * Ls + s];
 #pragma unroll
     for (int k = 0; k < 3; ++k) c[k] = *reinterpret_cast<const uint4 *>(base + chunk_index<bf16>(site4, s, Ls, k));
-  }
-  template <typename R> __device__ void decode(R v[24]) const {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const uint32_t w[4] = {c[k].x, c[k].y, c[k].z, c[k].w};
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        v[8 * k + 2 * j] = (R)(bf16_to_float((uint16_t)(w[j] & 0xffffu)) * n);
-        v[8 * k + 2 * j + 1] = (R)(bf16_to_float((uint16_t)(w[j] >> 16)) * n);
-      }
-    }
   }
 };
 
@@ -291,51 +267,6 @@ template <typename R> __device__ inline void widen16(const bf16 *p, R *o) {
   for (int j = 0; j < 4; ++j) {
     o[2 * j] = (R)bf16_to_float((uint16_t)(w[j] & 0xffffu));
     o[2 * j + 1] = (R)bf16_to_float((uint16_t)(w[j] >> 16));
-  }
-}
-
-// ---------------------------------------------------------------- links
-// One 3x3 complex matrix = 18 reals [row][col][re,im]; stored in the
-// spinor storage type without a scale (|U_ij| <= 1).
-template <typename R>
-__device__ inline void load18(const double *base, size_t m, R u[18]) {
-  const double2 *p = reinterpret_cast<const double2 *>(base + m * 18);
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    double2 t = p[k];
-    u[2 * k] = (R)t.x;
-    u[2 * k + 1] = (R)t.y;
-  }
-}
-template <typename R>
-__device__ inline void load18(const float *base, size_t m, R u[18]) {
-  const float2 *p = reinterpret_cast<const float2 *>(base + m * 18);
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    float2 t = p[k];
-    u[2 * k] = (R)t.x;
-    u[2 * k + 1] = (R)t.y;
-  }
-}
-template <typename R>
-__device__ inline void load18(const _Float16 *base, size_t m, R u[18]) {
-  const uint32_t *p = reinterpret_cast<const uint32_t *>(base + m * 18);
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    union { uint32_t u; _Float16 h[2]; } c;
-    c.u = p[k];
-    u[2 * k] = (R)(float)c.h[0];
-    u[2 * k + 1] = (R)(float)c.h[1];
-  }
-}
-template <typename R>
-__device__ inline void load18(const bf16 *base, size_t m, R u[18]) {
-  const uint32_t *p = reinterpret_cast<const uint32_t *>(base + m * 18);
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    uint32_t w = p[k];
-    u[2 * k] = (R)bf16_to_float((uint16_t)(w & 0xffffu));
-    u[2 * k + 1] = (R)bf16_to_float((uint16_t)(w >> 16));
   }
 }
 
@@ -381,32 +312,6 @@ __device__ inline void project(const R v[24], R h[12]) {
   for (int k = 0; k < 12; ++k) h[k] = X[k] + Y[k];
 }
 
-// w = U h for both spins (U already includes the dagger of backward links),
-// written as chains of fused multiply-adds (4 per complex multiply-add).
-template <typename R>
-__device__ inline void link_mul(const R u[18], const R h[12], R w[12]) {
-#pragma unroll
-  for (int k = 0; k < 2; ++k)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const R *ua = u + a * 6;
-      const R *hk = h + k * 6;
-      R re = ua[0] * hk[0];
-      R im = ua[0] * hk[1];
-      re = fma(-ua[1], hk[1], re);
-      im = fma(ua[1], hk[0], im);
-#pragma unroll
-      for (int b = 1; b < 3; ++b) {
-        re = fma(ua[2 * b], hk[2 * b], re);
-        re = fma(-ua[2 * b + 1], hk[2 * b + 1], re);
-        im = fma(ua[2 * b], hk[2 * b + 1], im);
-        im = fma(ua[2 * b + 1], hk[2 * b], im);
-      }
-      w[(k * 3 + a) * 2] = re;
-      w[(k * 3 + a) * 2 + 1] = im;
-    }
-}
-
 // acc += (w, -SGN B^+ w) for one colour c: B_x^+ w = (i w1, i w0),
 // B_y^+ w = (w1, -w0), B_z^+ w = (i w0, -i w1), B_t^+ w = (w0, w1).
 template <int MU, int SGN, typename R>
@@ -431,14 +336,6 @@ __device__ inline void accumulate_colour(R acc[24], int c, R w0r, R w0i, R w1r, 
   }
   acc[(2 * 3 + c) * 2] = fma(n, l0r, acc[(2 * 3 + c) * 2]); acc[(2 * 3 + c) * 2 + 1] = fma(n, l0i, acc[(2 * 3 + c) * 2 + 1]);
   acc[(3 * 3 + c) * 2] = fma(n, l1r, acc[(3 * 3 + c) * 2]); acc[(3 * 3 + c) * 2 + 1] = fma(n, l1i, acc[(3 * 3 + c) * 2 + 1]);
-}
-
-template <int MU, int SGN, typename R>
-__device__ inline void accumulate(R acc[24], const R w[12]) {
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-    accumulate_colour<MU, SGN>(acc, c, w[(0 * 3 + c) * 2], w[(0 * 3 + c) * 2 + 1], w[(1 * 3 + c) * 2],
-                               w[(1 * 3 + c) * 2 + 1], R(1));
 }
 
 // One direction of the hop for one 5D site, given the projected neighbour
@@ -467,6 +364,78 @@ __device__ inline void hop_half(const R h[12], const R *U, R acc[24], R n) {
         re = fma(-ur[2 * b + 1], hk[2 * b + 1], re);
         im = fma(ur[2 * b], hk[2 * b + 1], im);
         im = fma(ur[2 * b + 1], hk[2 * b], im);
+      }
+      w[2 * k] = re;
+      w[2 * k + 1] = im;
+    }
+    accumulate_colour<MU, SGN>(acc, a, w[0], w[1], w[2], w[3], n);
+  }
+}
+
+// ---------------------------------------------------------------- FP16 packed projection and link product
+// F16 spinors keep each complex component as one 32-bit word (re in the low
+// half, im in the high half).  The projection is formed on these pairs with
+// packed half-precision adds (the multiplications by +-i and the signs fold
+// into the instructions' operand selects and negations), and the link product
+// uses two-term dot products of half pairs accumulated in FP32, so that every
+// product is exact and every sum is an FP32 sum.  The links of the workgroup
+// are staged as pairs A = (re U, -im U), B = (im U, re U) for each complex
+// entry: re(U h) = A . h and im(U h) = B . h.
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+__device__ inline half2_t as_half2(uint32_t w) { return __builtin_bit_cast(half2_t, w); }
+__device__ inline half2_t times_i(half2_t z) { return half2_t{-z.y, z.x}; }
+template <int SGN> __device__ inline half2_t sgn(half2_t z) { return SGN > 0 ? z : -z; }
+
+// the two parts X (upper spins) and Y = -SGN B l of the projection, as in
+// project_parts, on stored words; index k*3 + c for spin k, colour c
+template <int MU, int SGN>
+__device__ inline void project_parts_h16(const uint32_t w[12], half2_t X[6], half2_t Y[6]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const half2_t l0 = as_half2(w[6 + c]), l1 = as_half2(w[9 + c]);
+    X[c] = as_half2(w[c]);
+    X[3 + c] = as_half2(w[3 + c]);
+    if (MU == 0) {  // B l = (-i l1, -i l0)
+      Y[c] = sgn<SGN>(times_i(l1)); Y[3 + c] = sgn<SGN>(times_i(l0));
+    } else if (MU == 1) {  // B l = (-l1, l0)
+      Y[c] = sgn<SGN>(l1); Y[3 + c] = sgn<-SGN>(l0);
+    } else if (MU == 2) {  // B l = (-i l0, i l1)
+      Y[c] = sgn<SGN>(times_i(l0)); Y[3 + c] = sgn<-SGN>(times_i(l1));
+    } else {  // B l = l
+      Y[c] = sgn<-SGN>(l0); Y[3 + c] = sgn<-SGN>(l1);
+    }
+  }
+}
+
+// the link entry pairs (A, B) of one staged 16-byte chunk of F16 links (four
+// complex entries) -> eight words
+__device__ inline void link_pairs_h16(uint4 q, uint32_t *o) {
+  const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    o[2 * j] = w[j] ^ 0x80000000u;          // (re, -im)
+    o[2 * j + 1] = (w[j] >> 16) | (w[j] << 16);  // (im, re)
+  }
+}
+
+// hop_half for packed F16 half spinors: acc += n (U h, -SGN B^+ U h), U as
+// staged pairs (18 words, row-major), one colour row at a time
+template <int MU, int SGN>
+__device__ inline void hop_half_h16(const half2_t h[6], const uint32_t *U, float acc[24], float n) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    uint32_t ur[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ur[k] = U[6 * a + k];
+    float w[4];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      float re = 0.f, im = 0.f;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        re = __builtin_amdgcn_fdot2(as_half2(ur[2 * b]), h[3 * k + b], re, false);
+        im = __builtin_amdgcn_fdot2(as_half2(ur[2 * b + 1]), h[3 * k + b], im, false);
       }
       w[2 * k] = re;
       w[2 * k + 1] = im;

@@ -178,12 +178,56 @@ __device__ inline void hop_dir(R *lds, int nthr, int tid, int s, int Ls, R cu, R
 __device__ inline uint32_t rot_prev_word(uint32_t x) { return (uint32_t)rot_prev_dpp((int)x); }
 __device__ inline uint32_t rot_next_word(uint32_t x) { return (uint32_t)rot_next_dpp((int)x); }
 
-// The same for F16/BF16 inputs stored as v/n with a per-site norm n: the
-// projection works on the stored values (for F16 every widening folds into a
-// mixed-precision multiply-add, `one` being an opaque 1 that keeps the sum a
-// multiply-add) and n multiplies the link product as it is accumulated.  With
-// M_phi on the input the neighbours' norms enter the mixing coefficients as
-// n(s -+ 1)/n(s) (a zero site has no stored values and uses n = 1).
+// The stored words and norm of the upper spins at s-1 and the lower spins at
+// s+1 (the part of the neighbouring lanes' inputs that M_phi mixes in).
+// Must be reached by all threads of the workgroup.
+template <int XM, typename S>
+__device__ inline void exchange_pre_raw(float *lds, int nthr, int tid, int s, int Ls, const RawSite<S> &raw,
+                                        RawSite<S> &w, float &nm, float &np) {
+  if (XM == kXDpp16) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      w.set_word(i, rot_prev_word(raw.word(i)));
+      w.set_word(6 + i, rot_next_word(raw.word(6 + i)));
+    }
+    nm = rot_prev_dpp(raw.n);
+    np = rot_next_dpp(raw.n);
+  } else if (XM == kXPerm) {
+    const int lane = tid & 63;
+    const int am = 4 * ((s > 0) ? lane - 1 : lane + Ls - 1);
+    const int ap = 4 * ((s < Ls - 1) ? lane + 1 : lane - (Ls - 1));
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      w.set_word(i, (uint32_t)__builtin_amdgcn_ds_bpermute(am, (int)raw.word(i)));
+      w.set_word(6 + i, (uint32_t)__builtin_amdgcn_ds_bpermute(ap, (int)raw.word(6 + i)));
+    }
+    nm = perm(am, raw.n);
+    np = perm(ap, raw.n);
+  } else {
+    uint32_t *lw = reinterpret_cast<uint32_t *>(lds);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 12; ++i) lw[i * nthr + tid] = raw.word(i);
+    lds[12 * nthr + tid] = raw.n;
+    __syncthreads();
+    const int tm = (s > 0) ? tid - 1 : tid + Ls - 1;
+    const int tp = (s < Ls - 1) ? tid + 1 : tid - (Ls - 1);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      w.set_word(i, lw[i * nthr + tm]);
+      w.set_word(6 + i, lw[(6 + i) * nthr + tp]);
+    }
+    nm = lds[12 * nthr + tm];
+    np = lds[12 * nthr + tp];
+  }
+}
+
+// The same for BF16 inputs stored as v/n with a per-site norm n: the
+// projection works on the stored values (widened to FP32) and n multiplies
+// the link product as it is accumulated.  With M_phi on the input the
+// neighbours' norms enter the mixing coefficients as n(s -+ 1)/n(s) (a zero
+// site has no stored values and uses n = 1).  `one` is an opaque 1 that keeps
+// each sum a multiply-add.
 template <int MU, int SGN, int PRE, int XM, typename S>
 __device__ inline void hop_dir_norm(float *lds, int nthr, int tid, int s, int Ls, float cu, float cl, float one,
                                     const RawSite<S> &raw, const float *U, float acc[24]) {
@@ -202,44 +246,9 @@ __device__ inline void hop_dir_norm(float *lds, int nthr, int tid, int s, int Ls
   project_parts<MU, SGN>(v, X, Y);
   float n = raw.n;
   if (PRE) {
-    RawSite<S> w;  // the upper spins at s-1 and the lower spins at s+1, as stored
+    RawSite<S> w;
     float nm, np;
-    if (XM == kXDpp16) {
-#pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        w.set_word(i, rot_prev_word(raw.word(i)));
-        w.set_word(6 + i, rot_next_word(raw.word(6 + i)));
-      }
-      nm = rot_prev_dpp(n);
-      np = rot_next_dpp(n);
-    } else if (XM == kXPerm) {
-      const int lane = tid & 63;
-      const int am = 4 * ((s > 0) ? lane - 1 : lane + Ls - 1);
-      const int ap = 4 * ((s < Ls - 1) ? lane + 1 : lane - (Ls - 1));
-#pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        w.set_word(i, (uint32_t)__builtin_amdgcn_ds_bpermute(am, (int)raw.word(i)));
-        w.set_word(6 + i, (uint32_t)__builtin_amdgcn_ds_bpermute(ap, (int)raw.word(6 + i)));
-      }
-      nm = perm(am, n);
-      np = perm(ap, n);
-    } else {
-      uint32_t *lw = reinterpret_cast<uint32_t *>(lds);
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < 12; ++i) lw[i * nthr + tid] = raw.word(i);
-      lds[12 * nthr + tid] = n;
-      __syncthreads();
-      const int tm = (s > 0) ? tid - 1 : tid + Ls - 1;
-      const int tp = (s < Ls - 1) ? tid + 1 : tid - (Ls - 1);
-#pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        w.set_word(i, lw[i * nthr + tm]);
-        w.set_word(6 + i, lw[(6 + i) * nthr + tp]);
-      }
-      nm = lds[12 * nthr + tm];
-      np = lds[12 * nthr + tp];
-    }
+    exchange_pre_raw<XM>(lds, nthr, tid, s, Ls, raw, w, nm, np);
     float wv[24], Xw[12], Yw[12];
     w.decode_raw(wv);
     project_parts<MU, SGN>(wv, Xw, Yw);
@@ -253,6 +262,43 @@ __device__ inline void hop_dir_norm(float *lds, int nthr, int tid, int s, int Ls
     for (int k = 0; k < 12; ++k) h[k] = fmaf(X[k], one, Y[k]);
   }
   hop_half<MU, SGN>(h, U, acc, n);
+}
+
+// F16 inputs: the projected half spinor is formed in packed half precision
+// on the stored words and multiplied by the link with FP32-accumulated dot
+// products (hop_half_h16).  With M_phi on the input the three contributions
+// n(s)(X + Y)(s), cu n(s-1) X(s-1) and cl n(s+1) Y(s+1) are scaled by the
+// largest of their weights m, so that every coefficient is at most 1 and the
+// half-precision sum cannot overflow; m multiplies the link product.
+template <int MU, int SGN, int PRE, int XM>
+__device__ inline void hop_dir_h16(float *lds, int nthr, int tid, int s, int Ls, float cu, float cl,
+                                   const RawSite<_Float16> &raw, const uint32_t *U, float acc[24]) {
+  uint32_t wd[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) wd[i] = raw.word(i);
+  half2_t X[6], Y[6], h[6];
+  project_parts_h16<MU, SGN>(wd, X, Y);
+  float m = raw.n;
+  if (PRE) {
+    RawSite<_Float16> w;
+    float nm, np;
+    exchange_pre_raw<XM>(lds, nthr, tid, s, Ls, raw, w, nm, np);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) wd[i] = w.word(i);
+    half2_t Xw[6], Yw[6];
+    project_parts_h16<MU, SGN>(wd, Xw, Yw);
+    const float n = raw.n, wu = cu * nm, wl = cl * np;
+    m = fmaxf(n, fmaxf(fabsf(wu), fabsf(wl)));
+    m = m > 0.f ? m : 1.f;
+    const float rm = __builtin_amdgcn_rcpf(m);
+    const _Float16 a = (_Float16)(n * rm), bu = (_Float16)(wu * rm), bl = (_Float16)(wl * rm);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) h[k] = half2_t{a, a} * (X[k] + Y[k]) + (half2_t{bu, bu} * Xw[k] + half2_t{bl, bl} * Yw[k]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) h[k] = X[k] + Y[k];
+  }
+  hop_half_h16<MU, SGN>(h, U, acc, m);
 }
 
 // ---------------------------------------------------------------- dense fifth-dimension matrices
@@ -418,24 +464,38 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
   const int cb = active ? cbr : 0;
   const int self = GLOBAL ? cb : site;  // index of this site in tables and outputs
 
-  // the first neighbour spinor is requested before anything waits
-  const int *nb = a.nbr + (size_t)(active ? self : 0) * 8;
+  // The eight neighbour indices are loaded once, with two 16-byte loads, and
+  // kept in registers (rotated by two per direction pair below): no spinor
+  // load ever waits for an index load issued after an earlier spinor load.
+  int nbw[8];
+  {
+    const int4 *nb4 = reinterpret_cast<const int4 *>(a.nbr + (size_t)(active ? self : 0) * 8);
+    const int4 q0 = nb4[0], q1 = nb4[1];
+    const int qa[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+    for (int d = 0; d < 8; ++d) nbw[d] = active ? qa[d] : a.zero_site;
+  }
+  // the first neighbour spinor is requested before anything else waits
   const S *in = reinterpret_cast<const S *>(a.in);
   const size_t rin = (size_t)r * a.in_stride;
   RawSite<S> cur, nxt;
-  cur.load(in, a.in_norm, rin + (active ? nb[0] : a.zero_site), s, Ls);
+  cur.load(in, a.in_norm, rin + nbw[0], s, Ls);
 
   // the links of all sites of the workgroup, staged once into LDS with
-  // 16-byte loads (every link is used by all Ls x nrhs lanes of its site)
-  {
+  // 16-byte loads (every link is used by all Ls x nrhs lanes of its site);
+  // the lanes of a site stage that site's links, so no further index is read
+  constexpr bool kH16 = std::is_same<S, _Float16>::value;
+  if (lane_ok) {
     const S *links = reinterpret_cast<const S *>(a.links);
     constexpr int per = 16 / sizeof(S);
     constexpr int nchunk = 144 / per;
-    for (int i = tid; i < nsw * nchunk; i += nthr) {
-      const int q = i / nchunk, c = i - q * nchunk;
-      const int st = tile * nsw + q;
-      const int cq = st < a.nsites ? max(a.site_cb[st], 0) : 0;
-      widen16<R>(links + (size_t)cq * 144 + c * per, Lk + q * 144 + c * per);
+    const S *src = links + (size_t)(cbr >= 0 ? cbr : 0) * 144;
+    for (int c = s + Ls * r; c < nchunk; c += Ls * nrhs) {
+      if constexpr (kH16)  // F16: (A, B) pairs for the packed link product
+        link_pairs_h16(*reinterpret_cast<const uint4 *>(src + c * per),
+                       reinterpret_cast<uint32_t *>(Lk) + sl * 144 + c * 8);
+      else
+        widen16<R>(src + c * per, Lk + sl * 144 + c * per);
     }
   }
   if (EPI == EPI_DENSE) {
@@ -452,7 +512,7 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
   const R pc = PRE ? (R)(a.mphi_c / a.mphi_b) : R(0);
   const R pcu = pc * ((s > 0) ? R(1) : (R)(-a.mf));
   const R pcl = pc * ((s < Ls - 1) ? R(1) : (R)(-a.mf));
-  // an opaque 1 (see hop_dir_norm)
+  // an opaque 1 (BF16, see hop_dir_norm)
   float one = 1.f;
   asm volatile("" : "+s"(one));
   // One direction is always in flight ahead of the one being computed: the
@@ -462,20 +522,29 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
   // FP64 spinors are large: there the register budget is spent on occupancy
   // instead of the prefetch (each direction loads just before it is used).
   constexpr bool kPrefetch = sizeof(R) != 8;
+  // (nbw[0], nbw[1]) always hold the indices of directions 2 mu, 2 mu + 1
 #pragma unroll 1
   for (int mu = 0; mu < 4; ++mu) {
-    if (kPrefetch) nxt.load(in, a.in_norm, rin + (active ? nb[2 * mu + 1] : a.zero_site), s, Ls);
+    if (kPrefetch) nxt.load(in, a.in_norm, rin + nbw[1], s, Ls);
 #pragma unroll
     for (int bw = 0; bw < 2; ++bw) {
       const int d = 2 * mu + bw;
-      if (kPrefetch && bw == 1 && mu < 3) cur.load(in, a.in_norm, rin + (active ? nb[d + 1] : a.zero_site), s, Ls);
-      if (!kPrefetch && d > 0) cur.load(in, a.in_norm, rin + (active ? nb[d] : a.zero_site), s, Ls);
+      // (unconditional: after the last pair nbw[2] is direction 6 again, a
+      // cached reload; a load skipped on one path would make the wait
+      // before the backward direction drain every load in flight)
+      if (kPrefetch && bw == 1) cur.load(in, a.in_norm, rin + nbw[2], s, Ls);
+      if (!kPrefetch && d > 0) cur.load(in, a.in_norm, rin + nbw[bw], s, Ls);
       const R *U = Lsite + d * 18;
       // (1 - g_mu) for the forward hop of H and the backward hop of H^+
       constexpr int sp = (DAG != 0) ? -1 : 1;
       const int sg = bw ? -sp : sp;
 #define MSPCG_DIR(M)                                                                                        \
-  if constexpr (Traits<S>::kNorm) {                                                                         \
+  if constexpr (kH16) {                                                                                     \
+    const RawSite<S> &raw = (bw == 0 || !kPrefetch) ? cur : nxt;                                           \
+    const uint32_t *Uw = reinterpret_cast<const uint32_t *>(U);                                            \
+    if (sg > 0) hop_dir_h16<M, 1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, raw, Uw, acc);                  \
+    else hop_dir_h16<M, -1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, raw, Uw, acc);                        \
+  } else if constexpr (Traits<S>::kNorm) {                                                                  \
     const RawSite<S> &raw = (bw == 0 || !kPrefetch) ? cur : nxt;                                           \
     if (sg > 0) hop_dir_norm<M, 1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, one, raw, U, acc);             \
     else hop_dir_norm<M, -1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, one, raw, U, acc);                   \
@@ -493,6 +562,8 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
       }
 #undef MSPCG_DIR
     }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) nbw[k] = nbw[k + 2];
   }
 
   const R scale = (R)(PRE ? a.scale * a.mphi_b : a.scale);
