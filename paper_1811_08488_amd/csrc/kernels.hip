@@ -386,6 +386,61 @@ __device__ inline void dense_chiral(R *lds, const R *X, int nthr, int tid, int s
   }
 }
 
+// The same contraction where every wave holds whole (site, rhs) groups (the
+// DPP and ds_bpermute layouts: G groups of Ls lanes per wave): each wave
+// contracts only its own groups' columns, in its own slice of the LDS
+// structure of arrays, so no workgroup barrier is needed (a wave's LDS
+// accesses are served in order).  Per chirality the wave's 12 G columns
+// form ceil(12 G / 16) MFMA tiles; the X operand of a lane is the same for
+// every tile and is read once.  Needs Ls % 4 == 0 and Ls <= 32; X must be
+// visible to all waves (staged before a barrier).
+template <typename R>
+__device__ inline void dense_chiral_wave(R *lds, const R *X, int nthr, int tid, int Ls, int G, R scale, R v[24]) {
+  using T4 = typename V4<R>::T;
+  const int lane = tid & 63;
+  R *W = lds + (tid - lane);  // component k of the wave's lane j: W[k * nthr + j]
+#pragma unroll
+  for (int k = 0; k < 24; ++k) W[k * nthr + lane] = v[k];
+  const int row = lane & 15, kq = lane >> 4;
+  const int ncol = 12 * G, ntn = (ncol + 15) >> 4, nk = Ls >> 2;
+#pragma unroll
+  for (int chi = 0; chi < 2; ++chi) {
+    const R *Xc = X + chi * Ls * Ls;
+    R a0[8], a1[8];  // X[row][4 j + kq] and X[16 + row][4 j + kq], j < Ls / 4
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      a0[j] = (j < nk && row < Ls) ? Xc[row * Ls + 4 * j + kq] : R(0);
+      a1[j] = (j < nk && 16 + row < Ls) ? Xc[(16 + row) * Ls + 4 * j + kq] : R(0);
+    }
+    for (int nt = 0; nt < ntn; ++nt) {
+      const int col = nt * 16 + row;
+      const bool colok = col < ncol;
+      const int gi = colok ? col / 12 : 0;
+      R *Wc = W + (chi * 12 + (colok ? col - 12 * gi : 0)) * nthr + gi * Ls;
+      T4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (j < nk) {
+          const R b = colok ? Wc[4 * j + kq] : R(0);
+          c0 = mfma16x16x4(a0[j], b, c0);
+          if (Ls > 16) c1 = mfma16x16x4(a1[j], b, c1);
+        }
+      }
+      if (colok) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          // output rows: FP32 4(l/16) + i, FP64 4i + l/16 (as in dense_chiral)
+          const int m = (sizeof(R) == 8) ? 4 * i + kq : 4 * kq + i;
+          if (m < Ls) Wc[m] = scale * c0[i];
+          if (Ls > 16 && 16 + m < Ls) Wc[16 + m] = scale * c1[i];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 24; ++k) v[k] = W[k * nthr + lane];
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
 // with its own L2.  Renumbering them so that every XCD works on one
 // contiguous range of tiles keeps the neighbours a tile gathers (x, y and z
@@ -568,7 +623,10 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
 
   const R scale = (R)(PRE ? a.scale * a.mphi_b : a.scale);
   if (EPI == EPI_DENSE) {
-    dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * nsw, G, scale, acc, XM == kXLds);
+    if (XM != kXLds && (Ls & 3) == 0 && Ls <= 32)
+      dense_chiral_wave<R>(lds, Xl, nthr, tid, Ls, G, scale, acc);
+    else
+      dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * nsw, G, scale, acc, XM == kXLds);
   } else if (EPI == EPI_MPHIDAG || EPI == EPI_M5DAG_MPHIDAG) {
     pchi_comb<1, XM, R>(lds, nthr, tid, s, Ls, (R)a.mphi_b, (R)a.mphi_c, (R)a.mf, acc);
 #pragma unroll
@@ -692,14 +750,19 @@ __global__ void __launch_bounds__(256) op5_kernel(const Op5Args a) {
   R *Xl = lds + 24 * nthr;
   const int site = blockIdx.x * a.nsite_wg + sl;
   const bool active = lane_ok && site < a.nsites;
-  if (a.dense) {
-    const R *Xg = reinterpret_cast<const R *>(a.mat);
-    for (int i = tid; i < 2 * Ls * Ls; i += nthr) Xl[i] = Xg[i];
-  }
+  constexpr bool kWave = XM != kXLds;
+  const bool wave_dense = kWave && (Ls & 3) == 0 && Ls <= 32;
   R v[24];
   const size_t idx = (size_t)r * a.stride + (active ? site : 0);
   load24<R>(reinterpret_cast<const S *>(a.in), a.in_norm, idx, s, Ls, v);
-  if (a.dense)
+  if (a.dense) {
+    const R *Xg = reinterpret_cast<const R *>(a.mat);
+    for (int i = tid; i < 2 * Ls * Ls; i += nthr) Xl[i] = Xg[i];
+    if (wave_dense) __syncthreads();  // (dense_chiral has its own barrier)
+  }
+  if (a.dense && wave_dense)
+    dense_chiral_wave<R>(lds, Xl, nthr, tid, Ls, G, R(1), v);
+  else if (a.dense)
     dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * a.nsite_wg, G, R(1), v, false);
   else if (a.dag)
     pchi_comb<1, XM, R>(lds, nthr, tid, s, Ls, (R)a.a, (R)a.b, (R)a.mf, v);
