@@ -710,10 +710,13 @@ void run_block_cg(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int k, con
     BlockArgs ba4 = ba;
     ba4.nsite_wg = block_hops(h, bg, prec, nrhs, bg->p.v, bg->Ap.v, part, st);
     HIPCHK(block_scalars(0, ba4, part, scal, st));
-    HIPCHK(block_update_xr(prec, ba, bg->x.v, bg->r.v, bg->p.v, bg->Ap.v, scal, part, st));
     if (it + 1 < k) {
+      // r first (its norm gives beta), then x and p in one pass
+      HIPCHK(block_update_r(prec, ba, bg->r.v, bg->Ap.v, scal, part, st));
       HIPCHK(block_scalars(1, ba, part, scal, st));
-      HIPCHK(block_update_p(prec, ba, bg->p.v, bg->r.v, scal, st));
+      HIPCHK(block_update_xp(prec, ba, bg->x.v, bg->p.v, bg->r.v, scal, st));
+    } else {
+      HIPCHK(block_update_xr(prec, ba, bg->x.v, bg->r.v, bg->p.v, bg->Ap.v, scal, part, st));
     }
   }
   HIPCHK(block_scatter(prec, ba, z, bg->x.v, r, rr, n_total, partial_zr ? partial_zr : part, st));

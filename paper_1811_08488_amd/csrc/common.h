@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace mspcg {
 
 // ---------------------------------------------------------------- storage types
@@ -164,6 +166,23 @@ __device__ inline void store24(bf16 *base, float *norm, size_t site4, int s, int
       w[j] = (uint32_t)float_to_bf16((float)v[8 * k + 2 * j] * inv) |
              ((uint32_t)float_to_bf16((float)v[8 * k + 2 * j + 1] * inv) << 16);
     *reinterpret_cast<uint4 *>(base + chunk_index<bf16>(site4, s, Ls, k)) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+// The values a store24 of v followed by a load24 returns, computed in
+// registers (F16/BF16: the same per-site scaling and rounding).
+template <typename S, typename R>
+__device__ inline void stored_values(R v[24]) {
+  if constexpr (std::is_same<S, _Float16>::value) {
+    float inv;
+    const float n = site_scale(v, inv);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) v[k] = (R)((float)(_Float16)((float)v[k] * inv) * n);
+  } else if constexpr (std::is_same<S, bf16>::value) {
+    float inv;
+    const float n = site_scale(v, inv);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) v[k] = (R)(bf16_to_float(float_to_bf16((float)v[k] * inv)) * n);
   }
 }
 

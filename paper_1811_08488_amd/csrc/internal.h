@@ -121,12 +121,15 @@ hipError_t block_scatter(int prec, const BlockArgs &b, const Vec &zglob, const V
 //                   mode 1: rho_new = sum; beta = rho_new/rho (0 if rho = 0); rho = rho_new
 //                   mode 2: rho = sum (initialisation)
 hipError_t block_scalars(int mode, const BlockArgs &b, const double *partial, double *scal, hipStream_t st);
-// x += alpha p, r -= alpha Ap, partial |r|^2
+// x += alpha p, r -= alpha Ap, partial |r|^2 (the last inner iteration)
 hipError_t block_update_xr(int prec, const BlockArgs &b, const Vec &x, const Vec &r, const Vec &p, const Vec &Ap,
                            const double *scal, double *partial, hipStream_t st);
-// p = r + beta p
-hipError_t block_update_p(int prec, const BlockArgs &b, const Vec &p, const Vec &r, const double *scal,
-                          hipStream_t st);
+// r -= alpha Ap, partial |r|^2 (the other inner iterations) ...
+hipError_t block_update_r(int prec, const BlockArgs &b, const Vec &r, const Vec &Ap, const double *scal,
+                          double *partial, hipStream_t st);
+// ... then, once beta is known, x += alpha p and p = r + beta p
+hipError_t block_update_xp(int prec, const BlockArgs &b, const Vec &x, const Vec &p, const Vec &r, const double *scal,
+                           hipStream_t st);
 
 // scal layout per (block, rhs): [rho, alpha, beta, pad]
 constexpr int kScal = 4;

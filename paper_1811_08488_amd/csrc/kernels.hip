@@ -393,10 +393,13 @@ __device__ inline void dense_chiral(R *lds, const R *X, int nthr, int tid, int s
 // accesses are served in order).  Per chirality the wave's 12 G columns
 // form ceil(12 G / 16) MFMA tiles; the X operand of a lane is the same for
 // every tile and is read once.  Needs Ls % 4 == 0 and Ls <= 32; X must be
-// visible to all waves (staged before a barrier).
-template <typename R>
-__device__ inline void dense_chiral_wave(R *lds, const R *X, int nthr, int tid, int Ls, int G, R scale, R v[24]) {
+// visible to all waves (staged before a barrier).  LSC > 0 fixes Ls at
+// compile time (straight-line code for the common lengths), 0 reads it from Ls.
+template <typename R, int LSC>
+__device__ inline void dense_chiral_wave_t(R *lds, const R *X, int nthr, int tid, int Ls_rt, R scale, R v[24]) {
   using T4 = typename V4<R>::T;
+  const int Ls = LSC > 0 ? LSC : Ls_rt;
+  const int G = 64 / Ls;
   const int lane = tid & 63;
   R *W = lds + (tid - lane);  // component k of the wave's lane j: W[k * nthr + j]
 #pragma unroll
@@ -439,6 +442,17 @@ __device__ inline void dense_chiral_wave(R *lds, const R *X, int nthr, int tid, 
   }
 #pragma unroll
   for (int k = 0; k < 24; ++k) v[k] = W[k * nthr + lane];
+}
+template <typename R>
+__device__ inline void dense_chiral_wave(R *lds, const R *X, int nthr, int tid, int Ls, R scale, R v[24]) {
+  if (Ls == 16)
+    dense_chiral_wave_t<R, 16>(lds, X, nthr, tid, Ls, scale, v);
+  else if (Ls == 12)
+    dense_chiral_wave_t<R, 12>(lds, X, nthr, tid, Ls, scale, v);
+  else if (Ls == 8)
+    dense_chiral_wave_t<R, 8>(lds, X, nthr, tid, Ls, scale, v);
+  else
+    dense_chiral_wave_t<R, 0>(lds, X, nthr, tid, Ls, scale, v);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
@@ -624,7 +638,7 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
   const R scale = (R)(PRE ? a.scale * a.mphi_b : a.scale);
   if (EPI == EPI_DENSE) {
     if (XM != kXLds && (Ls & 3) == 0 && Ls <= 32)
-      dense_chiral_wave<R>(lds, Xl, nthr, tid, Ls, G, scale, acc);
+      dense_chiral_wave<R>(lds, Xl, nthr, tid, Ls, scale, acc);
     else
       dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * nsw, G, scale, acc, XM == kXLds);
   } else if (EPI == EPI_MPHIDAG || EPI == EPI_M5DAG_MPHIDAG) {
@@ -761,7 +775,7 @@ __global__ void __launch_bounds__(256) op5_kernel(const Op5Args a) {
     if (wave_dense) __syncthreads();  // (dense_chiral has its own barrier)
   }
   if (a.dense && wave_dense)
-    dense_chiral_wave<R>(lds, Xl, nthr, tid, Ls, G, R(1), v);
+    dense_chiral_wave<R>(lds, Xl, nthr, tid, Ls, R(1), v);
   else if (a.dense)
     dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * a.nsite_wg, G, R(1), v, false);
   else if (a.dag)
@@ -1067,7 +1081,7 @@ __global__ void __launch_bounds__(256) k_block_update_xr(const BlockArgs b, Vec 
     store24<R>(reinterpret_cast<S *>(xv.data), xv.norm, o, s, Ls, x);
     store24<R>(reinterpret_cast<S *>(rv.data), rv.norm, o, s, Ls, rr);
     // the norm is taken of the stored (rounded) residual
-    load24<R>(reinterpret_cast<const S *>(rv.data), rv.norm, o, s, Ls, rr);
+    stored_values<S>(rr);
     R acc = 0;
 #pragma unroll
     for (int k = 0; k < 24; ++k) acc += rr[k] * rr[k];
@@ -1076,21 +1090,60 @@ __global__ void __launch_bounds__(256) k_block_update_xr(const BlockArgs b, Vec 
   wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, b.nrhs, b.nsite_wg, 0, val, partial, blockIdx.x);
 }
 
+// r -= alpha Ap with the partial |r|^2 (every iteration but the last, where
+// k_block_update_xr also updates x)
 template <typename S>
-__global__ void __launch_bounds__(256) k_block_update_p(const BlockArgs b, Vec pv, Vec rv, const double *scal) {
+__global__ void __launch_bounds__(256) k_block_update_r(const BlockArgs b, Vec rv, Vec qv, const double *scal,
+                                                        double *partial) {
+  using R = typename Traits<S>::R;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nthr = blockDim.x, tid = threadIdx.x, Ls = b.Ls, G = b.nrhs * Ls;
+  const int sl = tid / G, rem = tid - sl * G, r = rem / Ls, s = rem - r * Ls;
+  const int site = blockIdx.x * b.nsite_wg + sl;
+  const int blk = site < b.nsites ? b.be_blk[site] : -1;
+  double val = 0;
+  if (blk >= 0) {
+    const R al = (R)scal[((size_t)blk * b.nrhs + r) * kScal + 1];
+    const size_t o = (size_t)r * rv.stride + site;
+    R rr[24], q[24];
+    load24<R>(reinterpret_cast<const S *>(rv.data), rv.norm, o, s, Ls, rr);
+    load24<R>(reinterpret_cast<const S *>(qv.data), qv.norm, o, s, Ls, q);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) rr[k] -= al * q[k];
+    store24<R>(reinterpret_cast<S *>(rv.data), rv.norm, o, s, Ls, rr);
+    stored_values<S>(rr);
+    R acc = 0;
+#pragma unroll
+    for (int k = 0; k < 24; ++k) acc += rr[k] * rr[k];
+    val = (double)acc;
+  }
+  wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, b.nrhs, b.nsite_wg, 0, val, partial, blockIdx.x);
+}
+
+// x += alpha p, then p = r + beta p (the x update of k_block_update_xr moved
+// here, where p is read anyway)
+template <typename S>
+__global__ void __launch_bounds__(256) k_block_update_xp(const BlockArgs b, Vec xv, Vec pv, Vec rv,
+                                                         const double *scal) {
   using R = typename Traits<S>::R;
   const int tid = threadIdx.x, Ls = b.Ls, G = b.nrhs * Ls;
   const int sl = tid / G, rem = tid - sl * G, r = rem / Ls, s = rem - r * Ls;
   const int site = blockIdx.x * b.nsite_wg + sl;
   const int blk = site < b.nsites ? b.be_blk[site] : -1;
   if (blk < 0) return;
-  const R be = (R)scal[((size_t)blk * b.nrhs + r) * kScal + 2];
+  const double *sc = scal + ((size_t)blk * b.nrhs + r) * kScal;
+  const R al = (R)sc[1], be = (R)sc[2];
   const size_t o = (size_t)r * pv.stride + site;
-  R p[24], rr[24];
+  R x[24], p[24], rr[24];
+  load24<R>(reinterpret_cast<const S *>(xv.data), xv.norm, o, s, Ls, x);
   load24<R>(reinterpret_cast<const S *>(pv.data), pv.norm, o, s, Ls, p);
   load24<R>(reinterpret_cast<const S *>(rv.data), rv.norm, o, s, Ls, rr);
 #pragma unroll
-  for (int k = 0; k < 24; ++k) p[k] = rr[k] + be * p[k];
+  for (int k = 0; k < 24; ++k) {
+    x[k] += al * p[k];
+    p[k] = rr[k] + be * p[k];
+  }
+  store24<R>(reinterpret_cast<S *>(xv.data), xv.norm, o, s, Ls, x);
   store24<R>(reinterpret_cast<S *>(pv.data), pv.norm, o, s, Ls, p);
 }
 
@@ -1170,11 +1223,19 @@ hipError_t block_update_xr(int prec, const BlockArgs &b, const Vec &x, const Vec
   return hipGetLastError();
 }
 
-hipError_t block_update_p(int prec, const BlockArgs &b, const Vec &p, const Vec &r, const double *scal,
-                          hipStream_t st) {
+hipError_t block_update_r(int prec, const BlockArgs &b, const Vec &r, const Vec &Ap, const double *scal,
+                          double *partial, hipStream_t st) {
   if (block_threads(b) > 256) return hipErrorInvalidValue;
-  MSPCG_PREC_SWITCH(prec, hipLaunchKernelGGL(k_block_update_p<S>, dim3(block_grid(b)), dim3(block_threads(b)), 0,
-                                             st, b, p, r, scal));
+  MSPCG_PREC_SWITCH(prec, hipLaunchKernelGGL(k_block_update_r<S>, dim3(block_grid(b)), dim3(block_threads(b)),
+                                             block_lds(b), st, b, r, Ap, scal, partial));
+  return hipGetLastError();
+}
+
+hipError_t block_update_xp(int prec, const BlockArgs &b, const Vec &x, const Vec &p, const Vec &r, const double *scal,
+                           hipStream_t st) {
+  if (block_threads(b) > 256) return hipErrorInvalidValue;
+  MSPCG_PREC_SWITCH(prec, hipLaunchKernelGGL(k_block_update_xp<S>, dim3(block_grid(b)), dim3(block_threads(b)), 0,
+                                             st, b, x, p, r, scal));
   return hipGetLastError();
 }
 
