@@ -218,7 +218,7 @@ def kernels_only(w, torch):
           flush=True)
 
 
-def study(w, torch, ks=(3, 4, 6, 8, 12, 18), inner_prec=None):
+def study(w, torch, ks=(3, 4, 6, 8, 12, 18), inner_prec=None, snake_modes=(0, 1)):
     """Inner-iteration sweep with and without the snake terms (Sec. 2.3, Sec. 3):
     outer iterations and time-to-solution for each k, plain CG for reference."""
     h, A, U, eps, b = build_problem(w, torch)
@@ -230,7 +230,7 @@ def study(w, torch, ks=(3, 4, 6, 8, 12, 18), inner_prec=None):
     rows.append({"solver": "cg", "outer_iters": st["outer_iters"], "seconds": st["seconds"],
                  "true_rel_resid": st["true_rel_resid"]})
     log(f"[study] plain CG: {st['outer_iters']} iterations, {st['seconds']:.3f}s")
-    for no_snake in (0, 1):
+    for no_snake in snake_modes:
         for k in ks:
             for rep in range(2):  # the first solve of a shape tunes and captures
                 x.data.zero_()
@@ -257,13 +257,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--study", action="store_true",
                     help="sweep the inner iterations k with and without the snake terms instead of the benchmark")
+    ap.add_argument("--study-k", default="3,4,6,8,12,18", help="inner iteration counts of the study")
+    ap.add_argument("--study-snake-only", action="store_true", help="study: skip the runs without snake terms")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only launch dslash_eo (F64/F32/F16) and a plain F64 copy of the same size, 10 times each "
                          "(the workload for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (the method's "
-              "sharding is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path (sharding the "
+              "lattice over GPUs, with halo exchange for the outer operator, is not implemented)",
+              file=sys.stderr)
         sys.exit(2)
     # the solvers report progress every 50 outer iterations (long solves on the large lattices)
     os.environ.setdefault("MSPCG_VERBOSE", "50")
@@ -280,7 +283,8 @@ def main():
         kernels_only(w, torch)
         return
     if args.study:
-        study(w, torch, inner_prec=args.inner_prec)
+        study(w, torch, ks=tuple(int(v) for v in args.study_k.split(",")), inner_prec=args.inner_prec,
+              snake_modes=(0,) if args.study_snake_only else (0, 1))
         return
     h, A, U, eps, b = build_problem(w, torch)
     x = h.field(M.F64, w.nrhs, 0)
