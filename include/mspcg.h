@@ -95,7 +95,9 @@ typedef struct {
 typedef struct {
   int nblk[4];           /* Dirichlet blocks per dimension (uneven splits allowed) */
   int n_inner;           /* fixed number k of inner CG iterations (>= 0) */
-  mspcg_prec inner_prec; /* storage of the inner solve: F32, F16 or BF16 (F64 allowed for tests) */
+  mspcg_prec inner_prec; /* storage of the inner solve: F32, F16 or BF16 (F64 allowed for tests);
+                          * arithmetic is FP32, except that F16 hops form the projected half
+                          * spinor in half precision and sum exact half products in FP32 */
   int no_snake;          /* 0 (default): A_s = P_s A P_s with its snake terms (Sec. 2.3);
                           * 1: every hop cut at the block boundary (P_s H P_s), which drops
                           * the snake terms -- the variant Sec. 2.3 argues against, for comparison */

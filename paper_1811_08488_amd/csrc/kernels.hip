@@ -5,8 +5,9 @@
 // Thread layout of every site kernel: a workgroup owns `nsite_wg` 4D sites of
 // a site list; its threads are (site, rhs, s) with s fastest, so one 4D site's
 // Ls x nrhs spinors are handled by consecutive lanes (coalesced loads of the
-// [rhs][site][s][24] layout, one broadcast link load per direction) and the
-// fifth-dimension coupling is an exchange between neighbouring lanes through LDS.
+// [rhs][site][chunk][s] layout, links staged once per site) and the
+// fifth-dimension coupling is an exchange between neighbouring lanes (DPP row
+// rotation, ds_bpermute or LDS, by the exchange mode below).
 #include <algorithm>
 #include <type_traits>
 
