@@ -101,6 +101,12 @@ typedef struct {
   int no_snake;          /* 0 (default): A_s = P_s A P_s with its snake terms (Sec. 2.3);
                           * 1: every hop cut at the block boundary (P_s H P_s), which drops
                           * the snake terms -- the variant Sec. 2.3 argues against, for comparison */
+  double inner_tol;      /* 0 (default): exactly n_inner iterations per block (Sec. 3);
+                          * > 0: precision-based stopping, the alternative Sec. 3 rejects, for
+                          * comparison: a block stops (keeps its iterate) after the first iteration
+                          * whose |r_s| <= inner_tol |P_s r|; n_inner is the maximum.  Frozen blocks
+                          * still occupy the batched launches, so this changes the preconditioner,
+                          * not the cost of an application.  Negative or non-finite: MSPCG_EINVAL */
 } mspcg_precond;
 
 typedef struct {

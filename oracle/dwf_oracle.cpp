@@ -461,12 +461,16 @@ void block_op(const Ctx &C0, const int *nblk, int s, int truncated, Field &out, 
 // Textbook CG for a fixed number k of iterations from a zero guess
 // (Sec. 3: "inner iterations"; Sec. 2.4: zero initial guess, one sweep).
 // If the residual or the curvature <p,A p> vanishes the iteration stops and
-// keeps the current iterate.
-void cg_fixed(const Ctx &C, const int *nblk, int s, int truncated, int k, Field &x, const Field &rhs) {
+// keeps the current iterate.  tol > 0: the precision-based stopping that
+// Sec. 3 sets aside -- stop after the first iteration whose residual norm is
+// at most tol times the initial one (k is then the maximum).
+void cg_fixed(const Ctx &C, const int *nblk, int s, int truncated, int k, Field &x, const Field &rhs,
+              double tol = 0.0) {
   const Params &P = C.P;
   x = field(P);
   Field r = rhs, p = rhs, q;
   double rr = norm2(r);
+  const double rr0 = rr;
   for (int it = 0; it < k; ++it) {
     if (rr == 0.0) break;
     block_op(C, nblk, s, truncated, q, p);
@@ -475,6 +479,7 @@ void cg_fixed(const Ctx &C, const int *nblk, int s, int truncated, int k, Field 
     double alpha = rr / pq;
     for (size_t i = 0; i < x.size(); ++i) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
     double rr_new = norm2(r);
+    if (tol > 0.0 && rr_new <= tol * tol * rr0) break;
     double beta = rr_new / rr;
     for (size_t i = 0; i < p.size(); ++i) p[i] = r[i] + beta * p[i];
     rr = rr_new;
@@ -483,7 +488,8 @@ void cg_fixed(const Ctx &C, const int *nblk, int s, int truncated, int k, Field 
 
 // Preconditioner of Sec. 2.4: z = M^{-1} r with M = (+)_s A_s, each block's
 // system solved by k inner CG iterations: z = sum_s P_s CG_k(A_s, P_s r).
-void local_block_cg(const Ctx &C, const int *nblk, int k, int truncated, Field &z, const Field &r) {
+void local_block_cg(const Ctx &C, const int *nblk, int k, int truncated, Field &z, const Field &r,
+                    double tol = 0.0) {
   const Params &P = C.P;
   int nb = nblk[0] * nblk[1] * nblk[2] * nblk[3];
   z = field(P);
@@ -491,7 +497,7 @@ void local_block_cg(const Ctx &C, const int *nblk, int k, int truncated, Field &
     Field rs = r, zs;
     mask_block(P, nblk, s, rs);
     mask_parity(P, rs, 0);
-    cg_fixed(C, nblk, s, truncated, k, zs, rs);
+    cg_fixed(C, nblk, s, truncated, k, zs, rs, tol);
     for (size_t i = 0; i < z.size(); ++i) z[i] += zs[i];
   }
 }
@@ -504,10 +510,10 @@ void local_block_cg(const Ctx &C, const int *nblk, int k, int truncated, Field &
 struct SolveResult { int iters; double true_rel; int converged; };
 
 SolveResult pcg(const Ctx &C, const int *nblk, int k, int truncated, double tol, int maxiter,
-                int reliable, Field &x, const Field &b, double *hist, int hist_len) {
+                int reliable, Field &x, const Field &b, double *hist, int hist_len, double inner_tol = 0.0) {
   const Params &P = C.P;
   auto precond = [&](Field &z, const Field &r) {
-    if (nblk) local_block_cg(C, nblk, k, truncated, z, r);
+    if (nblk) local_block_cg(C, nblk, k, truncated, z, r, inner_tol);
     else z = r;
   };
   double bb = norm2(b);
@@ -768,12 +774,12 @@ int oracle_block_op(const int *L, int Ls, const double *p, const double *U, doub
 
 // z = sum_s P_s CG_k(A_s, P_s r) on even sites
 int oracle_local_block_cg(const int *L, int Ls, const double *p, const double *U, double *z,
-                          const double *r, const int *nblk, int k, int truncated) {
+                          const double *r, const int *nblk, int k, int truncated, double inner_tol) {
   Ctx C;
-  if (!make_ctx(L, Ls, p, U, C) || !valid_blocks(C.P, nblk) || k < 0) return -1;
+  if (!make_ctx(L, Ls, p, U, C) || !valid_blocks(C.P, nblk) || k < 0 || !(inner_tol >= 0.0)) return -1;
   Field rf, zf;
   unpack(C.P, rf, r, 0);
-  local_block_cg(C, nblk, k, truncated, zf, rf);
+  local_block_cg(C, nblk, k, truncated, zf, rf, inner_tol);
   pack(C.P, z, zf, 0);
   return 0;
 }
@@ -784,13 +790,14 @@ int oracle_local_block_cg(const int *L, int Ls, const double *p, const double *U
 // [2] = 1 if converged.  hist (optional) receives ||r_k||/||b|| for k < hist_len.
 int oracle_solve(const int *L, int Ls, const double *p, const double *U, double *x, const double *b,
                  const int *nblk, int k, int truncated, double tol, int maxiter, int reliable,
-                 double *out_stats, double *hist, int hist_len) {
+                 double *out_stats, double *hist, int hist_len, double inner_tol) {
   Ctx C;
-  if (!make_ctx(L, Ls, p, U, C) || (nblk && !valid_blocks(C.P, nblk)) || maxiter < 0) return -1;
+  if (!make_ctx(L, Ls, p, U, C) || (nblk && !valid_blocks(C.P, nblk)) || maxiter < 0 || !(inner_tol >= 0.0))
+    return -1;
   Field xf, bf;
   unpack(C.P, xf, x, 0);
   unpack(C.P, bf, b, 0);
-  SolveResult r = pcg(C, nblk, k, truncated, tol, maxiter, reliable, xf, bf, hist, hist_len);
+  SolveResult r = pcg(C, nblk, k, truncated, tol, maxiter, reliable, xf, bf, hist, hist_len, inner_tol);
   pack(C.P, x, xf, 0);
   if (out_stats) { out_stats[0] = r.iters; out_stats[1] = r.true_rel; out_stats[2] = r.converged; }
   return 0;

@@ -77,6 +77,42 @@ def test_snake_terms_only_near_the_boundary():
             assert np.abs(d).max() > 1e-3 * scale
 
 
+def test_inner_tol_zero_is_fixed_k(small):
+    A, U = small
+    r = H.rand_c(np.random.default_rng(31), (A.V // 2, A.Ls, 4, 3))
+    for k in (1, 4):
+        assert np.array_equal(O.local_block_cg(A, U, r, (2, 1, 1, 2), k),
+                              O.local_block_cg(A, U, r, (2, 1, 1, 2), k, inner_tol=0.0))
+
+
+def test_inner_tol_stops_each_block_at_its_first_crossing(small):
+    """Precision-based stopping (Sec. 3, the alternative to a fixed k): every
+    block's result equals fixed-k CG on that block with k the first iteration
+    count whose residual |P_s r - A_s z_s| is at most tol |P_s r| (kmax if
+    none), found by brute force over k with the fixed-k oracle."""
+    A, U = small
+    nblk, kmax, tol = (2, 1, 1, 2), 8, 0.045
+    r = H.rand_c(np.random.default_rng(32), (A.V // 2, A.Ls, 4, 3))
+    fixed = {k: O.local_block_cg(A, U, r, nblk, k) for k in range(1, kmax + 1)}
+    got = O.local_block_cg(A, U, r, nblk, kmax, inner_tol=tol)
+    stops = []
+    for b in range(int(np.prod(nblk))):
+        m = block_mask(A.L, nblk, b, A.Ls)
+        rs = r * m
+        kstar = kmax
+        for k in range(1, kmax + 1):
+            res = np.linalg.norm(rs - O.block_op(A, U, fixed[k] * m, nblk, b)) / np.linalg.norm(rs)
+            assert abs(res - tol) > 1e-6 * tol  # no borderline decision
+            if res <= tol:
+                kstar = k
+                break
+        stops.append(kstar)
+        want = fixed[kstar] * m
+        assert np.linalg.norm(got * m - want) <= 1e-12 * np.linalg.norm(want), (b, kstar)
+    # the criterion is reached, at different iterations in different blocks
+    assert max(stops) < kmax and len(set(stops)) > 1, stops
+
+
 def test_inner_cg_k1_closed_form(small):
     A, U = small
     nblk = (2, 2, 2, 2)
