@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -13,6 +14,12 @@
 #include <vector>
 
 #include "internal.h"
+
+namespace mspcg {
+// Precision-based inner stopping (inner_stop.hip): mode 0 after the initial
+// block scalars, 1 after alpha, 2 after the new residual norm.
+hipError_t inner_stop(int mode, int nblocks, int nrhs, double tol, double *scal, double *stop, hipStream_t st);
+}  // namespace mspcg
 
 using namespace mspcg;
 
@@ -108,6 +115,7 @@ struct BlockGeom {
   // work vectors (inner precision)
   int vprec = -1, vnrhs = 0;
   OwnedVec x, r, p, Ap, o1v, e2v;
+  DBuf stopbuf;  // precision-based inner stopping: [nb * nrhs][2] (inner_stop.hip)
   DBuf partial, scal, rrbuf;
 };
 
@@ -695,8 +703,8 @@ BlockArgs block_args(mspcg_handle *h, BlockGeom *bg, int nrhs) {
 // The preconditioner: z = sum_s P_s CG_k(A_s, P_s r) for every (block, rhs).
 // r, z: FP64 even fields.  rr: device |r|^2 per rhs (RMS scaling); partial_zr
 // (optional): workgroup partials of Re<z, r> for the outer solver.
-void run_block_cg(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int k, const Vec &z, const Vec &r,
-                  const double *rr, double *partial_zr, int *nparts_zr, hipStream_t st) {
+void run_block_cg(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int k, double inner_tol, const Vec &z,
+                  const Vec &r, const double *rr, double *partial_zr, int *nparts_zr, hipStream_t st) {
   ensure_links(h, prec, st);
   ensure_block_vecs(h, bg, prec, nrhs);
   const int Ls = h->par.Ls;
@@ -704,16 +712,26 @@ void run_block_cg(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int k, con
   const double n_total = (double)h->Vh * Ls * 24;
   double *part = bg->partial.as<double>();
   double *scal = bg->scal.as<double>();
+  // inner_tol > 0: precision-based stopping (inner_stop.hip), else exactly k iterations
+  const bool stop = inner_tol > 0.0;
+  double *stopd = nullptr;
+  if (stop) {
+    bg->stopbuf.ensure((size_t)bg->nb * nrhs * 2 * sizeof(double));
+    stopd = bg->stopbuf.as<double>();
+  }
   HIPCHK(block_gather(prec, ba, bg->x.v, bg->r.v, bg->p.v, r, rr, n_total, part, st));
   HIPCHK(block_scalars(2, ba, part, scal, st));
+  if (stop) HIPCHK(inner_stop(0, bg->nb, nrhs, inner_tol, scal, stopd, st));
   for (int it = 0; it < k; ++it) {
     BlockArgs ba4 = ba;
     ba4.nsite_wg = block_hops(h, bg, prec, nrhs, bg->p.v, bg->Ap.v, part, st);
     HIPCHK(block_scalars(0, ba4, part, scal, st));
+    if (stop) HIPCHK(inner_stop(1, bg->nb, nrhs, inner_tol, scal, stopd, st));
     if (it + 1 < k) {
       // r first (its norm gives beta), then x and p in one pass
       HIPCHK(block_update_r(prec, ba, bg->r.v, bg->Ap.v, scal, part, st));
       HIPCHK(block_scalars(1, ba, part, scal, st));
+      if (stop) HIPCHK(inner_stop(2, bg->nb, nrhs, inner_tol, scal, stopd, st));
       HIPCHK(block_update_xp(prec, ba, bg->x.v, bg->p.v, bg->r.v, scal, st));
     } else {
       HIPCHK(block_update_xr(prec, ba, bg->x.v, bg->r.v, bg->p.v, bg->Ap.v, scal, part, st));
@@ -744,6 +762,7 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
     if (pc) {
       if (pc->n_inner < 0) fail(MSPCG_EINVAL, "n_inner < 0");
       if (pc->inner_prec < MSPCG_F64 || pc->inner_prec > MSPCG_BF16) fail(MSPCG_EINVAL, "bad inner precision");
+      if (!(pc->inner_tol >= 0.0) || !std::isfinite(pc->inner_tol)) fail(MSPCG_EINVAL, "inner_tol < 0 or not finite");
     }
     // the caller's fields may still be written by work on other streams
     HIPCHK(hipDeviceSynchronize());
@@ -796,7 +815,7 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
     };
     auto precond_launch = [&] {
       int nparts = 0;
-      run_block_cg(h, bg, pc->inner_prec, nrhs, pc->n_inner, Z, R, w.rr, part, &nparts, st);
+      run_block_cg(h, bg, pc->inner_prec, nrhs, pc->n_inner, pc->inner_tol, Z, R, w.rr, part, &nparts, st);
       HIPCHK(blas_reduce(part, nparts, nrhs, w.tmp, st));
     };
     auto precond = [&] {  // z = M^{-1} r and rho_new = <z, r> into w.tmp
@@ -808,8 +827,11 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
         precond_launch();
         return;
       }
-      const std::vector<intptr_t> key = {(intptr_t)bg, pc->inner_prec, nrhs, pc->n_inner, (intptr_t)Z.data,
-                                         (intptr_t)R.data, (intptr_t)w.rr, (intptr_t)part, (intptr_t)w.tmp};
+      int64_t tol_bits;
+      std::memcpy(&tol_bits, &pc->inner_tol, sizeof tol_bits);
+      const std::vector<intptr_t> key = {(intptr_t)bg, pc->inner_prec, nrhs, pc->n_inner, (intptr_t)tol_bits,
+                                         (intptr_t)Z.data, (intptr_t)R.data, (intptr_t)w.rr, (intptr_t)part,
+                                         (intptr_t)w.tmp};
       auto it = h->graphs.find(key);
       if (it != h->graphs.end()) {
         HIPCHK(hipGraphLaunch(it->second, st));
@@ -1101,6 +1123,7 @@ mspcg_status local_block_cg(mspcg_handle *h, mspcg_field *z, const mspcg_field *
     if (z->nrhs != r->nrhs) fail(MSPCG_EINVAL, "nrhs mismatch");
     if (pc->n_inner < 0) fail(MSPCG_EINVAL, "n_inner < 0");
     if (pc->inner_prec < MSPCG_F64 || pc->inner_prec > MSPCG_BF16) fail(MSPCG_EINVAL, "bad inner precision");
+    if (!(pc->inner_tol >= 0.0) || !std::isfinite(pc->inner_tol)) fail(MSPCG_EINVAL, "inner_tol < 0 or not finite");
     hipStream_t st = S(stream);
     BlockGeom *bg = get_blocks(h, pc->nblk, pc->no_snake, st);
     const int nrhs = r->nrhs;
@@ -1110,7 +1133,8 @@ mspcg_status local_block_cg(mspcg_handle *h, mspcg_field *z, const mspcg_field *
     double *rr = bg->rrbuf.as<double>();
     HIPCHK(blas_dot_partial((const double *)r->data, (const double *)r->data, n, nrhs, h->partial.as<double>(), st));
     HIPCHK(blas_reduce(h->partial.as<double>(), kBlasGrid, nrhs, rr, st));
-    run_block_cg(h, bg, pc->inner_prec, nrhs, pc->n_inner, vec_of(h, z), vec_of(h, r), rr, nullptr, nullptr, st);
+    run_block_cg(h, bg, pc->inner_prec, nrhs, pc->n_inner, pc->inner_tol, vec_of(h, z), vec_of(h, r), rr, nullptr,
+                 nullptr, st);
   });
 }
 

@@ -69,6 +69,40 @@ def test_local_block_cg_without_snake_terms(S, k):
     assert rel(S.h.download(fz)[0], want) <= 1e-11
 
 
+@pytest.mark.parametrize("prec,tol", [(M.F64, 1e-11), (M.F32, 1e-4)], ids=["f64", "f32"])
+def test_local_block_cg_precision_stopping(S, prec, tol):
+    """inner_tol > 0 (the stopping rule Sec. 3 sets aside): each block keeps the
+    iterate of the first iteration that meets the criterion, as in the oracle."""
+    nblk, kmax, itol = SMALL[2], 8, 0.095  # blocks stop after 6 and 5 iterations
+    r = S.rand(1, 77)
+    fz = S.h.field(M.F64, 1, 0)
+    S.h.local_block_cg(fz, S.h.upload(r, 0), nblk, kmax, prec, inner_tol=itol)
+    got = S.h.download(fz)[0]
+    want = O.local_block_cg(S.oa, S.U, r[0], nblk, kmax, inner_tol=itol)
+    assert rel(got, want) <= tol, rel(got, want)
+    # the criterion is met before kmax: the result is not the fixed-k one
+    assert rel(want, O.local_block_cg(S.oa, S.U, r[0], nblk, kmax)) > 1e-6
+
+
+def test_mspcg_precision_stopping_matches_oracle(S):
+    nblk = SMALL[2]
+    b = S.rand(1, 99)[0]
+    xo, st_o = O.solve(S.oa, S.U, b, nblk=nblk, k=8, tol=1e-10, maxiter=2000, inner_tol=0.1)
+    fx = S.h.field(M.F64, 1, 0)
+    st = S.h.mspcg_solve(fx, S.h.upload(b, 0), nblk, 8, M.F64, tol=1e-10, inner_tol=0.1)
+    assert st["status"] == M.OK
+    assert rel(S.h.download(fx)[0], xo) <= 1e-8
+    assert abs(st["outer_iters"] - st_o.iters) <= 2 + 0.02 * st_o.iters
+
+
+def test_precision_stopping_rejects_bad_tolerance(S):
+    for bad in (-0.1, float("nan"), float("inf")):
+        with pytest.raises(M.MspcgError) as e:
+            S.h.local_block_cg(S.h.field(M.F64, 1, 0), S.h.upload(S.rand(1, 78), 0), SMALL[2], 2, M.F32,
+                               inner_tol=bad)
+        assert e.value.status == M.EINVAL
+
+
 def test_mspcg_without_snake_terms_matches_oracle(S):
     nblk = SMALL[2]
     b = S.rand(1, 97)[0]
