@@ -107,6 +107,12 @@ typedef struct {
                           * whose |r_s| <= inner_tol |P_s r|; n_inner is the maximum.  Frozen blocks
                           * still occupy the batched launches, so this changes the preconditioner,
                           * not the cost of an application.  Negative or non-finite: MSPCG_EINVAL */
+  int n_sweeps;          /* multisplitting sweeps per application: 0 or 1 (default) is the paper's
+                          * single sweep from a zero guess (Sec. 2.4); s > 1 keeps s steps of the
+                          * multisplitting iteration (Sec. 2.1), the data of neighbouring blocks
+                          * entering through the full residual: z <- z + M (r - A z), with M the
+                          * one-sweep preconditioner -- one more FP64 A and one more block solve
+                          * per sweep.  Negative: MSPCG_EINVAL */
 } mspcg_precond;
 
 typedef struct {

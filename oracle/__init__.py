@@ -70,8 +70,8 @@ def _declare(L):
         "oracle_prepare_rhs": [_P, _I, _P, _P, _P, _P, _P],
         "oracle_reconstruct": [_P, _I, _P, _P, _P, _P, _P],
         "oracle_block_op": [_P, _I, _P, _P, _P, _P, _P, _I, _I],
-        "oracle_local_block_cg": [_P, _I, _P, _P, _P, _P, _P, _I, _I, _D],
-        "oracle_solve": [_P, _I, _P, _P, _P, _P, _P, _I, _I, _D, _I, _I, _P, _P, _I, _D],
+        "oracle_local_block_cg": [_P, _I, _P, _P, _P, _P, _P, _I, _I, _D, _I],
+        "oracle_solve": [_P, _I, _P, _P, _P, _P, _P, _I, _I, _D, _I, _I, _P, _P, _I, _D, _I],
         "oracle_num_threads": [],
         "oracle_set_num_threads": [_I],
     }
@@ -237,15 +237,17 @@ def block_op(A: Action, U, psi, nblk, block: int, truncated: bool = False) -> np
     return out
 
 
-def local_block_cg(A: Action, U, r, nblk, k: int, truncated: bool = False, inner_tol: float = 0.0) -> np.ndarray:
+def local_block_cg(A: Action, U, r, nblk, k: int, truncated: bool = False, inner_tol: float = 0.0,
+                   sweeps: int = 1) -> np.ndarray:
     """z = sum_s P_s CG_k(A_s, P_s r) (Sec. 2.4).  inner_tol > 0: each block stops after the first
-    iteration with |r_s| <= inner_tol |P_s r| (the precision-based stopping Sec. 3 sets aside)."""
+    iteration with |r_s| <= inner_tol |P_s r| (the precision-based stopping Sec. 3 sets aside).
+    sweeps > 1: further multisplitting sweeps z <- z + M (r - A z) (Sec. 2.1)."""
     U, r = _c128(U), _c128(r)
     z = np.zeros(_cb_shape(A), np.complex128)
     _check(
         lib().oracle_local_block_cg(
             A.cL(), A.Ls, A.cp(), _ptr(U), _ptr(z), _ptr(r), (ctypes.c_int * 4)(*nblk), k, int(truncated),
-            float(inner_tol),
+            float(inner_tol), int(sweeps),
         ),
         "local_block_cg",
     )
@@ -261,7 +263,7 @@ class SolveStats:
 
 
 def solve(A: Action, U, b, x0=None, nblk=None, k: int = 0, truncated: bool = False, tol: float = 1e-10,
-          maxiter: int = 10000, reliable: int = 50, hist_len: int = 0, inner_tol: float = 0.0):
+          maxiter: int = 10000, reliable: int = 50, hist_len: int = 0, inner_tol: float = 0.0, sweeps: int = 1):
     """Algorithm 1 on D_PC^+ D_PC x = b.  nblk=None: plain CG; else MSPCG with k inner CG iterations."""
     U, b = _c128(U), _c128(b)
     x = np.zeros(_cb_shape(A), np.complex128) if x0 is None else _c128(x0).copy()
@@ -271,7 +273,7 @@ def solve(A: Action, U, b, x0=None, nblk=None, k: int = 0, truncated: bool = Fal
     _check(
         lib().oracle_solve(
             A.cL(), A.Ls, A.cp(), _ptr(U), _ptr(x), _ptr(b), nb, k, int(truncated), tol, maxiter, reliable,
-            _ptr(st), _ptr(hist), hist_len, float(inner_tol),
+            _ptr(st), _ptr(hist), hist_len, float(inner_tol), int(sweeps),
         ),
         "solve",
     )

@@ -502,6 +502,23 @@ void local_block_cg(const Ctx &C, const int *nblk, int k, int truncated, Field &
   }
 }
 
+// Multisplitting with several sweeps (Sec. 2.1: the multisplitting
+// iteration; Sec. 2.4 keeps one sweep from a zero guess): each further sweep
+// solves the blocks again on the residual of the current iterate, so that the
+// neighbouring blocks' data enter through A z:  z <- z + M (r - A z).
+void multisplit(const Ctx &C, const int *nblk, int k, int truncated, double tol, int sweeps, Field &z,
+                const Field &r) {
+  local_block_cg(C, nblk, k, truncated, z, r, tol);
+  for (int sw = 1; sw < sweeps; ++sw) {
+    Field az, t, dz;
+    mdagm(C, az, z, 0);
+    t.resize(r.size());
+    axpby(t, 1.0, r, -1.0, az);
+    local_block_cg(C, nblk, k, truncated, dz, t, tol);
+    for (size_t i = 0; i < z.size(); ++i) z[i] += dz[i];
+  }
+}
+
 // Preconditioned CG, Algorithm 1 of Sec. 2.4, on A x = b (even sites).
 // Convergence reading: the recursive residual test ||r|| <= tol ||b|| is
 // confirmed by the true residual b - A x, which also replaces r every
@@ -510,10 +527,11 @@ void local_block_cg(const Ctx &C, const int *nblk, int k, int truncated, Field &
 struct SolveResult { int iters; double true_rel; int converged; };
 
 SolveResult pcg(const Ctx &C, const int *nblk, int k, int truncated, double tol, int maxiter,
-                int reliable, Field &x, const Field &b, double *hist, int hist_len, double inner_tol = 0.0) {
+                int reliable, Field &x, const Field &b, double *hist, int hist_len, double inner_tol = 0.0,
+                int sweeps = 1) {
   const Params &P = C.P;
   auto precond = [&](Field &z, const Field &r) {
-    if (nblk) local_block_cg(C, nblk, k, truncated, z, r, inner_tol);
+    if (nblk) multisplit(C, nblk, k, truncated, inner_tol, sweeps, z, r);
     else z = r;
   };
   double bb = norm2(b);
@@ -774,12 +792,13 @@ int oracle_block_op(const int *L, int Ls, const double *p, const double *U, doub
 
 // z = sum_s P_s CG_k(A_s, P_s r) on even sites
 int oracle_local_block_cg(const int *L, int Ls, const double *p, const double *U, double *z,
-                          const double *r, const int *nblk, int k, int truncated, double inner_tol) {
+                          const double *r, const int *nblk, int k, int truncated, double inner_tol, int sweeps) {
   Ctx C;
-  if (!make_ctx(L, Ls, p, U, C) || !valid_blocks(C.P, nblk) || k < 0 || !(inner_tol >= 0.0)) return -1;
+  if (!make_ctx(L, Ls, p, U, C) || !valid_blocks(C.P, nblk) || k < 0 || !(inner_tol >= 0.0) || sweeps < 0)
+    return -1;
   Field rf, zf;
   unpack(C.P, rf, r, 0);
-  local_block_cg(C, nblk, k, truncated, zf, rf, inner_tol);
+  multisplit(C, nblk, k, truncated, inner_tol, sweeps, zf, rf);
   pack(C.P, z, zf, 0);
   return 0;
 }
@@ -790,14 +809,15 @@ int oracle_local_block_cg(const int *L, int Ls, const double *p, const double *U
 // [2] = 1 if converged.  hist (optional) receives ||r_k||/||b|| for k < hist_len.
 int oracle_solve(const int *L, int Ls, const double *p, const double *U, double *x, const double *b,
                  const int *nblk, int k, int truncated, double tol, int maxiter, int reliable,
-                 double *out_stats, double *hist, int hist_len, double inner_tol) {
+                 double *out_stats, double *hist, int hist_len, double inner_tol, int sweeps) {
   Ctx C;
-  if (!make_ctx(L, Ls, p, U, C) || (nblk && !valid_blocks(C.P, nblk)) || maxiter < 0 || !(inner_tol >= 0.0))
+  if (!make_ctx(L, Ls, p, U, C) || (nblk && !valid_blocks(C.P, nblk)) || maxiter < 0 || !(inner_tol >= 0.0) ||
+      sweeps < 0)
     return -1;
   Field xf, bf;
   unpack(C.P, xf, x, 0);
   unpack(C.P, bf, b, 0);
-  SolveResult r = pcg(C, nblk, k, truncated, tol, maxiter, reliable, xf, bf, hist, hist_len, inner_tol);
+  SolveResult r = pcg(C, nblk, k, truncated, tol, maxiter, reliable, xf, bf, hist, hist_len, inner_tol, sweeps);
   pack(C.P, x, xf, 0);
   if (out_stats) { out_stats[0] = r.iters; out_stats[1] = r.true_rel; out_stats[2] = r.converged; }
   return 0;

@@ -113,6 +113,30 @@ def test_inner_tol_stops_each_block_at_its_first_crossing(small):
     assert max(stops) < kmax and len(set(stops)) > 1, stops
 
 
+def test_multisplit_sweeps_are_block_jacobi_steps():
+    """Several multisplitting sweeps (Sec. 2.1) with exact block solves: s sweeps
+    give sum_{j<s} (I - B A)^j B r with B = (+)_s A_s^{-1} the exact block inverse
+    (dense matrices on 2^3x4 x Ls=4), and one sweep is the single-sweep
+    preconditioner unchanged."""
+    A = O.Action((2, 2, 2, 4), 4, **MOB)
+    U = synth.gauge_field(A.L, 0.5, 91)
+    nblk = (1, 1, 1, 2)
+    shape = (A.V // 2, A.Ls, 4, 3)
+    Ad = H.dense_of(lambda v: O.mdagm(A, U, v), shape)
+    B = np.zeros_like(Ad)
+    for b in range(2):
+        Ms, idx, _ = dense_block_op(A, U, nblk, b)
+        B[np.ix_(idx, idx)] = np.linalg.inv(Ms)
+    r = H.rand_c(np.random.default_rng(33), shape)
+    k = 200  # CG on each 384-dimensional block converges to rounding
+    assert np.array_equal(O.local_block_cg(A, U, r, nblk, 5), O.local_block_cg(A, U, r, nblk, 5, sweeps=1))
+    IBA = np.eye(len(Ad)) - B @ Ad
+    for sweeps in (1, 2, 3):
+        want = sum(np.linalg.matrix_power(IBA, j) for j in range(sweeps)) @ (B @ r.ravel())
+        got = O.local_block_cg(A, U, r, nblk, k, sweeps=sweeps).ravel()
+        assert np.linalg.norm(got - want) <= 1e-9 * np.linalg.norm(want), sweeps
+
+
 def test_inner_cg_k1_closed_form(small):
     A, U = small
     nblk = (2, 2, 2, 2)
