@@ -218,11 +218,13 @@ def kernels_only(w, torch):
           flush=True)
 
 
-def study(w, torch, ks=(3, 4, 6, 8, 12, 18), inner_prec=None, snake_modes=(0, 1), inner_tols=(0.0,)):
+def study(w, torch, ks=(3, 4, 6, 8, 12, 18), inner_prec=None, snake_modes=(0, 1), inner_tols=(0.0,), sweeps=(1,),
+          max_iter=20000):
     """Inner-iteration sweep with and without the snake terms (Sec. 2.3, Sec. 3):
     outer iterations and time-to-solution for each k, plain CG for reference.
     inner_tols > 0 add runs with precision-based inner stopping (k the maximum),
-    the alternative to a fixed k that Sec. 3 sets aside."""
+    the alternative to a fixed k that Sec. 3 sets aside; sweeps > 1 add runs
+    with several multisplitting sweeps per preconditioner application (Sec. 2.1)."""
     h, A, U, eps, b = build_problem(w, torch)
     x = h.field(M.F64, w.nrhs, 0)
     prec = PREC[inner_prec or w.inner_prec]
@@ -233,17 +235,18 @@ def study(w, torch, ks=(3, 4, 6, 8, 12, 18), inner_prec=None, snake_modes=(0, 1)
                  "true_rel_resid": st["true_rel_resid"]})
     log(f"[study] plain CG: {st['outer_iters']} iterations, {st['seconds']:.3f}s")
     for no_snake in snake_modes:
-        for itol in inner_tols:
-            for k in ks:
-                for rep in range(2):  # the first solve of a shape tunes and captures
-                    x.data.zero_()
-                    st = h.mspcg_solve(x, b, w.nblk, k, prec, tol=w.tol, max_iter=20000, reliable=w.reliable,
-                                       no_snake=no_snake, inner_tol=itol)
-                rows.append({"solver": "mspcg", "k": k, "snake_terms": not no_snake, "inner_tol": itol,
-                             "status": st["status"], "outer_iters": st["outer_iters"], "seconds": st["seconds"],
-                             "true_rel_resid": st["true_rel_resid"]})
-                log(f"[study] k={k} snake={not no_snake} inner_tol={itol:g}: {st['outer_iters']} outer, "
-                    f"{st['seconds']:.3f}s")
+        for nsw in sweeps:
+            for itol in inner_tols:
+                for k in ks:
+                    for rep in range(2):  # the first solve of a shape tunes and captures
+                        x.data.zero_()
+                        st = h.mspcg_solve(x, b, w.nblk, k, prec, tol=w.tol, max_iter=max_iter,
+                                           reliable=w.reliable, no_snake=no_snake, inner_tol=itol, n_sweeps=nsw)
+                    rows.append({"solver": "mspcg", "k": k, "snake_terms": not no_snake, "inner_tol": itol,
+                                 "sweeps": nsw, "status": st["status"], "outer_iters": st["outer_iters"],
+                                 "seconds": st["seconds"], "true_rel_resid": st["true_rel_resid"]})
+                    log(f"[study] k={k} snake={not no_snake} inner_tol={itol:g} sweeps={nsw}: "
+                        f"{st['outer_iters']} outer, {st['seconds']:.3f}s")
     print(json.dumps({"study": "inner iterations and snake terms", "workload": w.name,
                       "inner_prec": inner_prec or w.inner_prec, "blocks": list(w.nblk), "tol": w.tol, "rows": rows}),
           flush=True)
@@ -263,6 +266,8 @@ def main():
                     help="sweep the inner iterations k with and without the snake terms instead of the benchmark")
     ap.add_argument("--study-k", default="3,4,6,8,12,18", help="inner iteration counts of the study")
     ap.add_argument("--study-snake-only", action="store_true", help="study: skip the runs without snake terms")
+    ap.add_argument("--study-sweeps", default="1", help="study: multisplitting sweeps per preconditioner application")
+    ap.add_argument("--study-max-iter", type=int, default=20000, help="study: outer iteration limit of each solve")
     ap.add_argument("--study-inner-tol", default="0",
                     help="study: inner stopping tolerances (0 = fixed k; > 0: precision-based stopping, k the maximum)")
     ap.add_argument("--kernels-only", action="store_true",
@@ -291,7 +296,8 @@ def main():
     if args.study:
         study(w, torch, ks=tuple(int(v) for v in args.study_k.split(",")), inner_prec=args.inner_prec,
               snake_modes=(0,) if args.study_snake_only else (0, 1),
-              inner_tols=tuple(float(v) for v in args.study_inner_tol.split(",")))
+              inner_tols=tuple(float(v) for v in args.study_inner_tol.split(",")),
+              sweeps=tuple(int(v) for v in args.study_sweeps.split(",")), max_iter=args.study_max_iter)
         return
     h, A, U, eps, b = build_problem(w, torch)
     x = h.field(M.F64, w.nrhs, 0)

@@ -157,6 +157,7 @@ struct mspcg_handle {
   Mat5 m5inv, m5inv_t, x1, x3;
   // FP64 workspaces
   OwnedVec tmp_o, tmp_e, tmp_o2, tmp_e2, sr, sp, sq, sz;
+  OwnedVec sw_t, sw_z, sw_q;  // multisplitting sweeps: r - A z, the sweep's correction, A z
   DBuf partial, scal;
   std::map<std::vector<int>, std::unique_ptr<BlockGeom>> blocks;
   // sites per workgroup chosen by the autotuner, per kernel variant and shape
@@ -741,9 +742,33 @@ void run_block_cg(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int k, dou
   if (nparts_zr) *nparts_zr = (ba.nsites + ba.nsite_wg - 1) / ba.nsite_wg;
 }
 
+// Further multisplitting sweeps (Sec. 2.1) after the first one in z:
+// z <- z + M (r - A z), M the one-sweep preconditioner applied by `apply_M`
+// (z, r, |r|^2 per rhs); FP64 temporaries owned by the handle.
+template <typename ApplyM>
+void more_sweeps(mspcg_handle *h, int nrhs, int sweeps, const Vec &z, const Vec &r, double *rr_tmp, double *part,
+                 hipStream_t st, ApplyM apply_M) {
+  const int Ls = h->par.Ls;
+  const long long n = (long long)h->Vh * Ls * 24;
+  h->sw_t.ensure(MSPCG_F64, nrhs, h->Vh, Ls);
+  h->sw_z.ensure(MSPCG_F64, nrhs, h->Vh, Ls);
+  h->sw_q.ensure(MSPCG_F64, nrhs, h->Vh, Ls);
+  ensure_fp64_temps(h, nrhs);
+  double *zd = (double *)z.data, *rd = (double *)r.data;
+  double *td = (double *)h->sw_t.v.data, *z2 = (double *)h->sw_z.v.data, *qd = (double *)h->sw_q.v.data;
+  for (int sw = 1; sw < sweeps; ++sw) {
+    apply_mdagm(h, MSPCG_F64, nrhs, h->sw_q.v, z, h->tmp_o.v, h->tmp_e.v, nullptr, st);
+    HIPCHK(blas_axpby(td, 1.0, rd, -1.0, qd, n, nrhs, st));  // t = r - A z
+    HIPCHK(blas_dot_partial(td, td, n, nrhs, part, st));
+    HIPCHK(blas_reduce(part, kBlasGrid, nrhs, rr_tmp, st));
+    apply_M(h->sw_z.v, h->sw_t.v, rr_tmp);
+    HIPCHK(blas_axpby(zd, 1.0, zd, 1.0, z2, n, nrhs, st));  // z += M t
+  }
+}
+
 // ------------------------------------------------------------- solvers
 struct SolverWork {
-  double *rho, *pap, *alpha, *beta, *rr, *bb, *tmp;
+  double *rho, *pap, *alpha, *beta, *rr, *bb, *tmp, *rrt, *zrt;
   int *active;
 };
 
@@ -763,6 +788,7 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
       if (pc->n_inner < 0) fail(MSPCG_EINVAL, "n_inner < 0");
       if (pc->inner_prec < MSPCG_F64 || pc->inner_prec > MSPCG_BF16) fail(MSPCG_EINVAL, "bad inner precision");
       if (!(pc->inner_tol >= 0.0) || !std::isfinite(pc->inner_tol)) fail(MSPCG_EINVAL, "inner_tol < 0 or not finite");
+      if (pc->n_sweeps < 0) fail(MSPCG_EINVAL, "n_sweeps < 0");
     }
     // the caller's fields may still be written by work on other streams
     HIPCHK(hipDeviceSynchronize());
@@ -777,7 +803,7 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
     if (pc) h->sz.ensure(MSPCG_F64, nrhs, h->Vh, Ls);
     const size_t nparts_max = std::max<size_t>((size_t)std::max(h->Vh, kBlasGrid), bg ? (size_t)bg->be_tot : 0);
     h->partial.ensure(nparts_max * nrhs * sizeof(double));
-    h->scal.ensure((size_t)nrhs * 8 * sizeof(double) + 64);
+    h->scal.ensure((size_t)nrhs * 10 * sizeof(double) + 64);
     double *part = h->partial.as<double>();
     SolverWork w;
     w.rho = h->scal.as<double>();
@@ -787,7 +813,9 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
     w.rr = w.beta + nrhs;
     w.bb = w.rr + nrhs;
     w.tmp = w.bb + nrhs;
-    w.active = reinterpret_cast<int *>(w.tmp + nrhs);
+    w.rrt = w.tmp + nrhs;
+    w.zrt = w.rrt + nrhs;
+    w.active = reinterpret_cast<int *>(w.zrt + nrhs);
     Vec X = vec_of(h, x), B = vec_of(h, b), R = h->sr.v, P = h->sp.v, Q = h->sq.v;
     Vec Z = pc ? h->sz.v : R;
     double *xd = (double *)X.data, *bd = (double *)B.data, *rd = (double *)R.data, *pd = (double *)P.data,
@@ -813,16 +841,13 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
       norm2(rd, w.rr);
       to_host(w.rr, hr);
     };
-    auto precond_launch = [&] {
-      int nparts = 0;
-      run_block_cg(h, bg, pc->inner_prec, nrhs, pc->n_inner, pc->inner_tol, Z, R, w.rr, part, &nparts, st);
-      HIPCHK(blas_reduce(part, nparts, nrhs, w.tmp, st));
-    };
-    auto precond = [&] {  // z = M^{-1} r and rho_new = <z, r> into w.tmp
-      if (!pc) {
-        HIPCHK(hipMemcpyAsync(w.tmp, w.rr, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
-        return;
-      }
+    // one sweep of the preconditioner: zv = M rv with <zv, rv> into zrv (rrv: |rv|^2)
+    auto precond_one = [&](const Vec &Zv, const Vec &Rv, double *rrv, double *zrv) {
+      auto precond_launch = [&] {
+        int nparts = 0;
+        run_block_cg(h, bg, pc->inner_prec, nrhs, pc->n_inner, pc->inner_tol, Zv, Rv, rrv, part, &nparts, st);
+        HIPCHK(blas_reduce(part, nparts, nrhs, zrv, st));
+      };
       if (!s->use_graph) {
         precond_launch();
         return;
@@ -830,8 +855,8 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
       int64_t tol_bits;
       std::memcpy(&tol_bits, &pc->inner_tol, sizeof tol_bits);
       const std::vector<intptr_t> key = {(intptr_t)bg, pc->inner_prec, nrhs, pc->n_inner, (intptr_t)tol_bits,
-                                         (intptr_t)Z.data, (intptr_t)R.data, (intptr_t)w.rr, (intptr_t)part,
-                                         (intptr_t)w.tmp};
+                                         (intptr_t)Zv.data, (intptr_t)Rv.data, (intptr_t)rrv, (intptr_t)part,
+                                         (intptr_t)zrv};
       auto it = h->graphs.find(key);
       if (it != h->graphs.end()) {
         HIPCHK(hipGraphLaunch(it->second, st));
@@ -856,6 +881,19 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
       HIPCHK(e);
       h->graphs[key] = exec;
     };
+    auto precond = [&] {  // z = M^{-1} r and rho_new = <z, r> into w.tmp
+      if (!pc) {
+        HIPCHK(hipMemcpyAsync(w.tmp, w.rr, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
+        return;
+      }
+      precond_one(Z, R, w.rr, w.tmp);
+      if (pc->n_sweeps > 1) {
+        more_sweeps(h, nrhs, pc->n_sweeps, Z, R, w.rrt, part, st,
+                    [&](const Vec &z2, const Vec &t, double *rrt) { precond_one(z2, t, rrt, w.zrt); });
+        HIPCHK(blas_dot_partial(zd, rd, n, nrhs, part, st));
+        HIPCHK(blas_reduce(part, kBlasGrid, nrhs, w.tmp, st));
+      }
+    };
     const double tol2 = s->tol * s->tol;
     norm2(bd, w.bb);
     to_host(w.bb, hb);
@@ -874,7 +912,7 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
     for (int a : active) any |= (a != 0);
     if (any) {
       precond();
-      if (pc) inner += pc->n_inner;
+      if (pc) inner += (long long)pc->n_inner * std::max(1, pc->n_sweeps);
       HIPCHK(blas_axpby(pd, 1.0, zd, 0.0, zd, n, nrhs, st));  // p = z
       HIPCHK(hipMemcpyAsync(w.rho, w.tmp, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
       while (it < s->max_iter) {
@@ -906,7 +944,7 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
         for (int a : active) any |= (a != 0);
         if (!any) break;
         precond();
-        if (pc) inner += pc->n_inner;
+        if (pc) inner += (long long)pc->n_inner * std::max(1, pc->n_sweeps);
         HIPCHK(solver_scalars(1, nrhs, w.active, w.rho, w.tmp, w.beta, st));
         HIPCHK(blas_xpay(pd, zd, w.beta, n, nrhs, st));
       }
@@ -1124,6 +1162,7 @@ mspcg_status local_block_cg(mspcg_handle *h, mspcg_field *z, const mspcg_field *
     if (pc->n_inner < 0) fail(MSPCG_EINVAL, "n_inner < 0");
     if (pc->inner_prec < MSPCG_F64 || pc->inner_prec > MSPCG_BF16) fail(MSPCG_EINVAL, "bad inner precision");
     if (!(pc->inner_tol >= 0.0) || !std::isfinite(pc->inner_tol)) fail(MSPCG_EINVAL, "inner_tol < 0 or not finite");
+    if (pc->n_sweeps < 0) fail(MSPCG_EINVAL, "n_sweeps < 0");
     hipStream_t st = S(stream);
     BlockGeom *bg = get_blocks(h, pc->nblk, pc->no_snake, st);
     const int nrhs = r->nrhs;
@@ -1135,6 +1174,14 @@ mspcg_status local_block_cg(mspcg_handle *h, mspcg_field *z, const mspcg_field *
     HIPCHK(blas_reduce(h->partial.as<double>(), kBlasGrid, nrhs, rr, st));
     run_block_cg(h, bg, pc->inner_prec, nrhs, pc->n_inner, pc->inner_tol, vec_of(h, z), vec_of(h, r), rr, nullptr,
                  nullptr, st);
+    if (pc->n_sweeps > 1) {
+      h->scal.ensure((size_t)nrhs * 10 * sizeof(double) + 64);
+      more_sweeps(h, nrhs, pc->n_sweeps, vec_of(h, z), vec_of(h, r), h->scal.as<double>(), h->partial.as<double>(), st,
+                  [&](const Vec &z2, const Vec &t, double *rrt) {
+                    run_block_cg(h, bg, pc->inner_prec, nrhs, pc->n_inner, pc->inner_tol, z2, t, rrt, nullptr,
+                                 nullptr, st);
+                  });
+    }
   });
 }
 

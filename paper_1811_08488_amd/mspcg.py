@@ -39,7 +39,7 @@ class CField(ctypes.Structure):
 
 class Precond(ctypes.Structure):
     _fields_ = [("nblk", ctypes.c_int * 4), ("n_inner", ctypes.c_int), ("inner_prec", ctypes.c_int),
-                ("no_snake", ctypes.c_int), ("inner_tol", ctypes.c_double)]
+                ("no_snake", ctypes.c_int), ("inner_tol", ctypes.c_double), ("n_sweeps", ctypes.c_int)]
 
 
 class Solver(ctypes.Structure):
@@ -254,13 +254,14 @@ class Handle:
         _check(lib().mdagm(self.h, ctypes.byref(out.c()), ctypes.byref(inp.c()), _stream(stream)))
 
     def block_apply(self, out: Field, inp: Field, nblk, prec=F64, stream=None, no_snake=0):
-        pc = Precond((ctypes.c_int * 4)(*nblk), 0, int(prec), int(no_snake), 0.0)
+        pc = Precond((ctypes.c_int * 4)(*nblk), 0, int(prec), int(no_snake), 0.0, 1)
         _check(lib().mspcg_block_apply(self.h, ctypes.byref(out.c()), ctypes.byref(inp.c()), ctypes.byref(pc),
                                        _stream(stream)))
 
     def local_block_cg(self, z: Field, r: Field, nblk, n_inner, inner_prec=F32, stream=None, no_snake=0,
-                       inner_tol=0.0):
-        pc = Precond((ctypes.c_int * 4)(*nblk), int(n_inner), int(inner_prec), int(no_snake), float(inner_tol))
+                       inner_tol=0.0, n_sweeps=1):
+        pc = Precond((ctypes.c_int * 4)(*nblk), int(n_inner), int(inner_prec), int(no_snake), float(inner_tol),
+                     int(n_sweeps))
         _check(lib().local_block_cg(self.h, ctypes.byref(z.c()), ctypes.byref(r.c()), ctypes.byref(pc),
                                     _stream(stream)))
 
@@ -280,8 +281,9 @@ class Handle:
         if precond is None:
             rc = lib().cg_solve(self.h, ctypes.byref(x.c()), ctypes.byref(b.c()), ctypes.byref(s), ctypes.byref(st))
         else:
-            nblk, k, prec, no_snake, inner_tol = precond
-            pc = Precond((ctypes.c_int * 4)(*nblk), int(k), int(prec), int(no_snake), float(inner_tol))
+            nblk, k, prec, no_snake, inner_tol, n_sweeps = precond
+            pc = Precond((ctypes.c_int * 4)(*nblk), int(k), int(prec), int(no_snake), float(inner_tol),
+                         int(n_sweeps))
             rc = lib().mspcg_solve(self.h, ctypes.byref(x.c()), ctypes.byref(b.c()), ctypes.byref(s),
                                    ctypes.byref(pc), ctypes.byref(st))
         _check(rc, allow=(OK, NOT_CONVERGED))
@@ -292,9 +294,9 @@ class Handle:
         return self._solve(x, b, tol, max_iter, reliable, None)
 
     def mspcg_solve(self, x: Field, b: Field, nblk, n_inner, inner_prec=F32, tol=1e-10, max_iter=10000,
-                    reliable=50, use_graph=1, no_snake=0, inner_tol=0.0):
-        return self._solve(x, b, tol, max_iter, reliable, (nblk, n_inner, inner_prec, no_snake, inner_tol),
-                           use_graph)
+                    reliable=50, use_graph=1, no_snake=0, inner_tol=0.0, n_sweeps=1):
+        return self._solve(x, b, tol, max_iter, reliable,
+                           (nblk, n_inner, inner_prec, no_snake, inner_tol, n_sweeps), use_graph)
 
     # -------------------------------------------------------- debug exports
     def site_maps(self, parity):

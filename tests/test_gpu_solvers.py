@@ -103,6 +103,39 @@ def test_precision_stopping_rejects_bad_tolerance(S):
         assert e.value.status == M.EINVAL
 
 
+@pytest.mark.parametrize("sweeps", [2, 3])
+def test_local_block_cg_multisplit_sweeps(S, sweeps):
+    """Several multisplitting sweeps z <- z + M (r - A z) (Sec. 2.1) through the
+    C ABI (FP64 inner) against the oracle."""
+    nblk = SMALL[2]
+    r = S.rand(2, 83 + sweeps)
+    fz = S.h.field(M.F64, 2, 0)
+    S.h.local_block_cg(fz, S.h.upload(r, 0), nblk, 4, M.F64, n_sweeps=sweeps)
+    got = S.h.download(fz)
+    for i in range(2):
+        want = O.local_block_cg(S.oa, S.U, r[i], nblk, 4, sweeps=sweeps)
+        assert rel(got[i], want) <= 1e-11, rel(got[i], want)
+        assert rel(want, O.local_block_cg(S.oa, S.U, r[i], nblk, 4)) > 1e-3  # not the one-sweep result
+
+
+def test_mspcg_multisplit_sweeps_matches_oracle(S):
+    nblk = SMALL[2]
+    b = S.rand(1, 98)[0]
+    xo, st_o = O.solve(S.oa, S.U, b, nblk=nblk, k=3, tol=1e-10, maxiter=2000, sweeps=2)
+    fx = S.h.field(M.F64, 1, 0)
+    st = S.h.mspcg_solve(fx, S.h.upload(b, 0), nblk, 3, M.F64, tol=1e-10, n_sweeps=2)
+    assert st["status"] == M.OK
+    assert rel(S.h.download(fx)[0], xo) <= 1e-8
+    assert abs(st["outer_iters"] - st_o.iters) <= 2 + 0.02 * st_o.iters
+    assert st["inner_iters"] in (6 * st["outer_iters"], 6 * (st["outer_iters"] + 1))
+
+
+def test_multisplit_sweeps_reject_negative(S):
+    with pytest.raises(M.MspcgError) as e:
+        S.h.local_block_cg(S.h.field(M.F64, 1, 0), S.h.upload(S.rand(1, 79), 0), SMALL[2], 2, M.F32, n_sweeps=-1)
+    assert e.value.status == M.EINVAL
+
+
 def test_mspcg_without_snake_terms_matches_oracle(S):
     nblk = SMALL[2]
     b = S.rand(1, 97)[0]
