@@ -219,7 +219,7 @@ def kernels_only(w, torch):
 
 
 def study(w, torch, ks=(3, 4, 6, 8, 12, 18), inner_prec=None, snake_modes=(0, 1), inner_tols=(0.0,), sweeps=(1,),
-          max_iter=20000):
+          max_iter=20000, reps=2):
     """Inner-iteration sweep with and without the snake terms (Sec. 2.3, Sec. 3):
     outer iterations and time-to-solution for each k, plain CG for reference.
     inner_tols > 0 add runs with precision-based inner stopping (k the maximum),
@@ -238,7 +238,7 @@ def study(w, torch, ks=(3, 4, 6, 8, 12, 18), inner_prec=None, snake_modes=(0, 1)
         for nsw in sweeps:
             for itol in inner_tols:
                 for k in ks:
-                    for rep in range(2):  # the first solve of a shape tunes and captures
+                    for rep in range(reps):  # the first solve of a shape tunes and captures
                         x.data.zero_()
                         st = h.mspcg_solve(x, b, w.nblk, k, prec, tol=w.tol, max_iter=max_iter,
                                            reliable=w.reliable, no_snake=no_snake, inner_tol=itol, n_sweeps=nsw)
@@ -268,6 +268,9 @@ def main():
     ap.add_argument("--study-snake-only", action="store_true", help="study: skip the runs without snake terms")
     ap.add_argument("--study-sweeps", default="1", help="study: multisplitting sweeps per preconditioner application")
     ap.add_argument("--study-max-iter", type=int, default=20000, help="study: outer iteration limit of each solve")
+    ap.add_argument("--study-no-snake-only", action="store_true", help="study: only the runs without snake terms")
+    ap.add_argument("--study-reps", type=int, default=2,
+                    help="study: solves per setting (the last is reported; the first also tunes and captures)")
     ap.add_argument("--study-inner-tol", default="0",
                     help="study: inner stopping tolerances (0 = fixed k; > 0: precision-based stopping, k the maximum)")
     ap.add_argument("--kernels-only", action="store_true",
@@ -295,9 +298,10 @@ def main():
         return
     if args.study:
         study(w, torch, ks=tuple(int(v) for v in args.study_k.split(",")), inner_prec=args.inner_prec,
-              snake_modes=(0,) if args.study_snake_only else (0, 1),
+              snake_modes=(0,) if args.study_snake_only else (1,) if args.study_no_snake_only else (0, 1),
               inner_tols=tuple(float(v) for v in args.study_inner_tol.split(",")),
-              sweeps=tuple(int(v) for v in args.study_sweeps.split(",")), max_iter=args.study_max_iter)
+              sweeps=tuple(int(v) for v in args.study_sweeps.split(",")), max_iter=args.study_max_iter,
+              reps=max(1, args.study_reps))
         return
     h, A, U, eps, b = build_problem(w, torch)
     x = h.field(M.F64, w.nrhs, 0)
