@@ -30,6 +30,38 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structures have the sizes and field offsets the C
+    compiler gives the header's structs (a field added on one side only would
+    shift every later field)."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"mspcg_dwf": M.Dwf, "mspcg_field": M.CField, "mspcg_precond": M.Precond,
+               "mspcg_solver": M.Solver, "mspcg_stats": M.Stats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mspcg.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        cname, field, value = line.split()
+        got[(cname, field)] = int(value)
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
 def _dwf(**kw):
     d = dict(L=(4, 4, 4, 4), Ls=8, M5=1.8, mf=0.01, b=1.0, c=0.0, t_bc=-1)
     d.update(kw)
