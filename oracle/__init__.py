@@ -71,7 +71,7 @@ def _declare(L):
         "oracle_reconstruct": [_P, _I, _P, _P, _P, _P, _P],
         "oracle_block_op": [_P, _I, _P, _P, _P, _P, _P, _I, _I],
         "oracle_local_block_cg": [_P, _I, _P, _P, _P, _P, _P, _I, _I, _D, _I],
-        "oracle_solve": [_P, _I, _P, _P, _P, _P, _P, _I, _I, _D, _I, _I, _P, _P, _I, _D, _I],
+        "oracle_solve": [_P, _I, _P, _P, _P, _P, _P, _I, _I, _D, _I, _I, _P, _P, _I, _D, _I, _I],
         "oracle_num_threads": [],
         "oracle_set_num_threads": [_I],
     }
@@ -263,8 +263,10 @@ class SolveStats:
 
 
 def solve(A: Action, U, b, x0=None, nblk=None, k: int = 0, truncated: bool = False, tol: float = 1e-10,
-          maxiter: int = 10000, reliable: int = 50, hist_len: int = 0, inner_tol: float = 0.0, sweeps: int = 1):
-    """Algorithm 1 on D_PC^+ D_PC x = b.  nblk=None: plain CG; else MSPCG with k inner CG iterations."""
+          maxiter: int = 10000, reliable: int = 50, hist_len: int = 0, inner_tol: float = 0.0, sweeps: int = 1,
+          flexible: bool = False):
+    """Algorithm 1 on D_PC^+ D_PC x = b.  nblk=None: plain CG; else MSPCG with k inner CG iterations.
+    flexible: the Polak-Ribiere beta <z', r' - r> / <z, r> instead of the printed Fletcher-Reeves one."""
     U, b = _c128(U), _c128(b)
     x = np.zeros(_cb_shape(A), np.complex128) if x0 is None else _c128(x0).copy()
     st = np.zeros(3, np.float64)
@@ -273,7 +275,7 @@ def solve(A: Action, U, b, x0=None, nblk=None, k: int = 0, truncated: bool = Fal
     _check(
         lib().oracle_solve(
             A.cL(), A.Ls, A.cp(), _ptr(U), _ptr(x), _ptr(b), nb, k, int(truncated), tol, maxiter, reliable,
-            _ptr(st), _ptr(hist), hist_len, float(inner_tol), int(sweeps),
+            _ptr(st), _ptr(hist), hist_len, float(inner_tol), int(sweeps), int(bool(flexible)),
         ),
         "solve",
     )

@@ -524,11 +524,16 @@ void multisplit(const Ctx &C, const int *nblk, int k, int truncated, double tol,
 // confirmed by the true residual b - A x, which also replaces r every
 // `reliable` iterations (reliable update; p is kept).
 // nblk == nullptr: M = 1 (plain CG, the comparison of Sec. 3).
+// flexible != 0: instead of the printed beta = <z', r'> / <z, r>
+// (Fletcher-Reeves), the Polak-Ribiere form beta = <z', r' - r> / <z, r>,
+// with r the residual before this iteration's update and r' the one the new
+// z' was computed from -- an option for preconditioners that are not fixed
+// linear maps (not the paper's algorithm).
 struct SolveResult { int iters; double true_rel; int converged; };
 
 SolveResult pcg(const Ctx &C, const int *nblk, int k, int truncated, double tol, int maxiter,
                 int reliable, Field &x, const Field &b, double *hist, int hist_len, double inner_tol = 0.0,
-                int sweeps = 1) {
+                int sweeps = 1, int flexible = 0) {
   const Params &P = C.P;
   auto precond = [&](Field &z, const Field &r) {
     if (nblk) multisplit(C, nblk, k, truncated, inner_tol, sweeps, z, r);
@@ -548,9 +553,11 @@ SolveResult pcg(const Ctx &C, const int *nblk, int k, int truncated, double tol,
   p = z;
   double rho = std::real(dot(r, z));
   int it = 0;
+  Field r_old;
   while (it < maxiter) {
     mdagm(C, q, p, 0);
     double alpha = rho / std::real(dot(p, q));
+    if (flexible) r_old = r;
     for (size_t i = 0; i < x.size(); ++i) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
     ++it;
     rr = norm2(r);
@@ -565,7 +572,7 @@ SolveResult pcg(const Ctx &C, const int *nblk, int k, int truncated, double tol,
     if (res.converged) break;
     precond(z, r);
     double rho_new = std::real(dot(z, r));
-    double beta = rho_new / rho;
+    double beta = flexible ? (rho_new - std::real(dot(z, r_old))) / rho : rho_new / rho;
     for (size_t i = 0; i < p.size(); ++i) p[i] = z[i] + beta * p[i];
     rho = rho_new;
   }
@@ -809,7 +816,7 @@ int oracle_local_block_cg(const int *L, int Ls, const double *p, const double *U
 // [2] = 1 if converged.  hist (optional) receives ||r_k||/||b|| for k < hist_len.
 int oracle_solve(const int *L, int Ls, const double *p, const double *U, double *x, const double *b,
                  const int *nblk, int k, int truncated, double tol, int maxiter, int reliable,
-                 double *out_stats, double *hist, int hist_len, double inner_tol, int sweeps) {
+                 double *out_stats, double *hist, int hist_len, double inner_tol, int sweeps, int flexible) {
   Ctx C;
   if (!make_ctx(L, Ls, p, U, C) || (nblk && !valid_blocks(C.P, nblk)) || maxiter < 0 || !(inner_tol >= 0.0) ||
       sweeps < 0)
@@ -817,7 +824,8 @@ int oracle_solve(const int *L, int Ls, const double *p, const double *U, double 
   Field xf, bf;
   unpack(C.P, xf, x, 0);
   unpack(C.P, bf, b, 0);
-  SolveResult r = pcg(C, nblk, k, truncated, tol, maxiter, reliable, xf, bf, hist, hist_len, inner_tol, sweeps);
+  SolveResult r = pcg(C, nblk, k, truncated, tol, maxiter, reliable, xf, bf, hist, hist_len, inner_tol, sweeps,
+                      flexible);
   pack(C.P, x, xf, 0);
   if (out_stats) { out_stats[0] = r.iters; out_stats[1] = r.true_rel; out_stats[2] = r.converged; }
   return 0;
