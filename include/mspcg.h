@@ -120,14 +120,23 @@ typedef struct {
   int max_iter;          /* outer iteration limit */
   int reliable_interval; /* replace r by b - A x every this many iterations (0: only at the end) */
   int use_graph;         /* capture the preconditioner in a hipGraph and replay it */
+  int timing;            /* 1: fill the time split of mspcg_stats (HIP events around each phase on the
+                          * solver's stream; the events add a few microseconds per iteration) */
+  int flexible_beta;     /* 0 (default): beta = <z', r'> / <z, r> as Algorithm 1 prints it (Fletcher-Reeves);
+                          * 1: beta = <z', r' - r> / <z, r> (Polak-Ribiere), which keeps consecutive search
+                          * directions A-conjugate when the preconditioner is not a fixed linear map (a fixed
+                          * number of inner CG iterations is not); one more FP64 dot product per iteration */
 } mspcg_solver;
 
 typedef struct {
   int outer_iters;          /* iterations of Algorithm 1 */
   long long inner_iters;    /* inner CG iterations summed over outer iterations (per block) */
   double *true_rel_resid;   /* caller-owned host array [nrhs], may be NULL */
-  double seconds;           /* wall time of the solve */
-  double t_precond;         /* seconds spent in the preconditioner (0 unless timing is on) */
+  double seconds;           /* wall time of the solve (host clock, includes set-up on first use) */
+  double t_outer_op;        /* seconds in the outer operator A = D_PC^+ D_PC (with mspcg_solver.timing) */
+  double t_precond;         /* seconds in the preconditioner, local_block_cg (with mspcg_solver.timing) */
+  double t_blas;            /* seconds in the outer vector updates and reductions (with mspcg_solver.timing);
+                             * all three are 0 when timing is off */
 } mspcg_stats;
 
 typedef struct mspcg_handle mspcg_handle;
@@ -159,9 +168,11 @@ mspcg_status mdagm(mspcg_handle *h, mspcg_field *out, const mspcg_field *in, voi
  * each A_s = P_s A P_s with its snake terms, Sec. 2.3): for every block s and
  * right-hand side independently, n_inner textbook CG iterations on
  * A_s z_s = P_s r from z_s = 0 (Sec. 3, fixed inner iterations), then
- * z = sum_s P_s z_s.  r and z are even F64 fields; the inner solve stores
- * its vectors in pc->inner_prec with FP32 arithmetic.  Each right-hand side
- * is scaled to unit RMS before the inner solve (CG_k is scale-equivariant). */
+ * z = sum_s P_s z_s.  r and z are even fields, both F64 or both F32 (F32 is
+ * widened to an F64 copy held by the handle and the result narrowed back);
+ * other storage types: MSPCG_EUNSUPPORTED.  The inner solve stores its
+ * vectors in pc->inner_prec with FP32 arithmetic.  Each right-hand side is
+ * scaled to unit RMS before the inner solve (CG_k is scale-equivariant). */
 mspcg_status local_block_cg(mspcg_handle *h, mspcg_field *z, const mspcg_field *r, const mspcg_precond *pc,
                             void *stream);
 
@@ -201,6 +212,21 @@ mspcg_status mspcg_debug_site_maps(mspcg_handle *h, int parity, int32_t *lex_of_
  * indices in the library's order. */
 mspcg_status mspcg_debug_block_sites(mspcg_handle *h, const int nblk[4], int block, int32_t counts[3],
                                      int32_t *be_lex, int32_t *o1_lex, int32_t *e2_lex);
+
+/* Measurement: launch one of the four hops of the block operator A_s
+ * (Sec. 2.3) for every block at once, `reps` times on `stream`, exactly as an
+ * inner CG iteration of local_block_cg launches it (same kernel, domain lists
+ * and tuned shape; storage pc->inner_prec, nrhs right-hand sides):
+ *   hop 1: B_e -> O1, M_phi on the input, dense M_phi M_5^{-1} epilogue
+ *   hop 2: O1 -> E2, plus M_5 applied to the block vector
+ *   hop 3: E2 -> O1, daggered, dense M_5^{-+} M_phi^+ epilogue
+ *   hop 4: O1 -> B_e, daggered, plus M_5^+ y, with the per-block <p, A_s p> partials
+ * on the handle's block work vectors as the last preconditioner call left
+ * them (zeros before any).  sites (may be NULL) receives the 4D sites of the
+ * launch's input and output domains, summed over blocks (padding excluded):
+ * {B_e, O1}, {O1, E2}, {E2, O1}, {O1, B_e} for hops 1..4. */
+mspcg_status mspcg_debug_block_hop(mspcg_handle *h, const mspcg_precond *pc, int nrhs, int hop, int reps,
+                                   long long sites[2], void *stream);
 
 /* Conversions between storage precisions of one parity (same layout). */
 mspcg_status mspcg_convert(mspcg_handle *h, mspcg_field *out, const mspcg_field *in, void *stream);

@@ -112,8 +112,10 @@ struct BlockGeom {
   std::vector<int> be_n, o1_n, e2_n;         // true counts
   std::vector<int> be_lex, o1_lex, e2_lex;   // lex per padded entry (-1 padding)
   DBuf d_be_cb, d_be_blk, d_be_nbr, d_be_e2, d_o1_cb, d_o1_nbr_be, d_o1_nbr_e2, d_e2_cb, d_e2_nbr, d_e2_be, d_be_off;
-  // work vectors (inner precision)
+  // work vectors (inner precision); `gen` changes whenever they are reallocated
+  // or cleared for another layout, so that graphs captured on them are never replayed
   int vprec = -1, vnrhs = 0;
+  long long gen = 0;
   OwnedVec x, r, p, Ap, o1v, e2v;
   DBuf stopbuf;  // precision-based inner stopping: [nb * nrhs][2] (inner_stop.hip)
   DBuf partial, scal, rrbuf;
@@ -158,6 +160,7 @@ struct mspcg_handle {
   // FP64 workspaces
   OwnedVec tmp_o, tmp_e, tmp_o2, tmp_e2, sr, sp, sq, sz;
   OwnedVec sw_t, sw_z, sw_q;  // multisplitting sweeps: r - A z, the sweep's correction, A z
+  OwnedVec lbc_r, lbc_z;      // local_block_cg on F32 fields: F64 copies of r and z
   DBuf partial, scal;
   std::map<std::vector<int>, std::unique_ptr<BlockGeom>> blocks;
   // sites per workgroup chosen by the autotuner, per kernel variant and shape
@@ -307,8 +310,10 @@ HopArgs base_args(mspcg_handle *h, int nrhs) {
 // variant/shape times every candidate with HIP events on the stream (the
 // kernels are pure functions of their inputs, so repeating them is harmless)
 // and keeps the fastest; the default shape wins ties within 3%.
+// may_tune = false (the allocation-free entry points): no timing, no events;
+// an untuned shape launches with the default and stays untuned.
 int run_hop(mspcg_handle *h, int list_kind, int prec, int dag, int pre, int epi, int dot, int global, HopArgs a,
-            hipStream_t st) {
+            hipStream_t st, bool may_tune = true) {
   const std::vector<int> key = {list_kind, prec, dag, pre, epi, dot, global, a.Ls, a.nrhs, a.nsites};
   auto it = h->tuned.find(key);
   int n = 0;
@@ -338,7 +343,7 @@ int run_hop(mspcg_handle *h, int list_kind, int prec, int dag, int pre, int epi,
           break;
         }
     n = n0;
-    if (h->autotune) {
+    if (h->autotune && may_tune) {
       hipEvent_t e0, e1;
       HIPCHK(hipEventCreate(&e0));
       HIPCHK(hipEventCreate(&e1));
@@ -366,7 +371,7 @@ int run_hop(mspcg_handle *h, int list_kind, int prec, int dag, int pre, int epi,
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
     }
-    h->tuned[key] = n;
+    if (may_tune) h->tuned[key] = n;
   }
   a.nsite_wg = n;
   HIPCHK(launch_hop(prec, dag, pre, epi, dot, global, a, st));
@@ -376,8 +381,9 @@ int run_hop(mspcg_handle *h, int list_kind, int prec, int dag, int pre, int epi,
 // Full-lattice hop: output parity p (site list = all cb), input parity 1-p.
 int global_hop(mspcg_handle *h, int prec, int nrhs, int p, const Vec &out, const Vec &in, int dag, int pre, int epi,
                double scale, const Mat5 *mat, const Vec *other, double *partial, const Vec *dotw,
-               hipStream_t st) {
-  ensure_links(h, prec, st);
+               hipStream_t st, bool may_tune = true) {
+  if (may_tune) ensure_links(h, prec, st);
+  else if (!h->links_ok[prec]) fail(MSPCG_EUNSUPPORTED, "links of this precision have not been prepared");
   HopArgs a = base_args(h, nrhs);
   a.nsites = h->Vh;
   a.site_cb = h->d_order[p].as<int>();
@@ -403,21 +409,22 @@ int global_hop(mspcg_handle *h, int prec, int nrhs, int p, const Vec &out, const
     a.dotw_norm = dotw->norm;
     a.dotw_stride = h->Vh;
   }
-  return run_hop(h, 0, prec, dag, pre, epi, partial ? 1 : 0, 1, a, st);
+  return run_hop(h, 0, prec, dag, pre, epi, partial ? 1 : 0, 1, a, st, may_tune);
 }
 
 // out_e = D_PC^+ D_PC in_e (all four hops fused with their fifth-dimension
 // neighbours); optional partial Re<in, out> per workgroup.
 int apply_mdagm(mspcg_handle *h, int prec, int nrhs, const Vec &out, const Vec &in, const Vec &to, const Vec &te,
-                double *partial, hipStream_t st) {
+                double *partial, hipStream_t st, bool may_tune = true) {
   // c_o = M_phi M_5^{-1} (-1/2 H_oe M_phi in)
-  global_hop(h, prec, nrhs, 1, to, in, 0, 1, EPI_DENSE, -0.5, &h->x1, nullptr, nullptr, nullptr, st);
+  global_hop(h, prec, nrhs, 1, to, in, 0, 1, EPI_DENSE, -0.5, &h->x1, nullptr, nullptr, nullptr, st, may_tune);
   // y_e = M_5 in + 1/2 H_eo c_o  (= D_PC in)
-  global_hop(h, prec, nrhs, 0, te, to, 0, 0, EPI_M5_OTHER, 0.5, nullptr, &in, nullptr, nullptr, st);
+  global_hop(h, prec, nrhs, 0, te, to, 0, 0, EPI_M5_OTHER, 0.5, nullptr, &in, nullptr, nullptr, st, may_tune);
   // f_o = M_5^{-+} M_phi^+ (-1/2 H^+_oe y_e)
-  global_hop(h, prec, nrhs, 1, to, te, 1, 0, EPI_DENSE, -0.5, &h->x3, nullptr, nullptr, nullptr, st);
+  global_hop(h, prec, nrhs, 1, to, te, 1, 0, EPI_DENSE, -0.5, &h->x3, nullptr, nullptr, nullptr, st, may_tune);
   // out = M_5^+ y + 1/2 M_phi^+ H^+_eo f  (= D_PC^+ y)
-  return global_hop(h, prec, nrhs, 0, out, to, 1, 0, EPI_M5DAG_MPHIDAG, 0.5, nullptr, &te, partial, &in, st);
+  return global_hop(h, prec, nrhs, 0, out, to, 1, 0, EPI_M5DAG_MPHIDAG, 0.5, nullptr, &te, partial, &in, st,
+                    may_tune);
 }
 
 void ensure_fp64_temps(mspcg_handle *h, int nrhs) {
@@ -602,9 +609,27 @@ BlockGeom *get_blocks(mspcg_handle *h, const int nblk[4], int no_snake, hipStrea
   return raw;
 }
 
+// Captured preconditioner graphs bake in the block work buffers: drop every
+// graph of `bg` (called when they are reallocated or cleared for a relayout;
+// the solvers synchronise before returning, so none is in flight).
+void drop_block_graphs(mspcg_handle *h, BlockGeom *bg) {
+  for (auto it = h->graphs.begin(); it != h->graphs.end();) {
+    if (!it->first.empty() && it->first[0] == (intptr_t)bg) {
+      (void)hipGraphExecDestroy(it->second);
+      it = h->graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
 void ensure_block_vecs(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs) {
   const int Ls = h->par.Ls;
   const bool relayout = bg->vprec != prec || bg->vnrhs != nrhs;
+  const std::vector<void *> before = {bg->x.data.p, bg->x.norm.p, bg->r.data.p, bg->r.norm.p, bg->p.data.p,
+                                      bg->p.norm.p, bg->Ap.data.p, bg->Ap.norm.p, bg->o1v.data.p, bg->o1v.norm.p,
+                                      bg->e2v.data.p, bg->e2v.norm.p, bg->partial.p, bg->scal.p, bg->rrbuf.p,
+                                      bg->stopbuf.p};
   // each list carries kPad extra sites after its last block: never written, so zero
   bg->x.ensure(prec, nrhs, bg->be_tot + kPad, Ls);
   bg->r.ensure(prec, nrhs, bg->be_tot + kPad, Ls);
@@ -616,6 +641,7 @@ void ensure_block_vecs(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs) {
   bg->partial.ensure((size_t)nwg * nrhs * sizeof(double));
   bg->scal.ensure((size_t)bg->nb * nrhs * kScal * sizeof(double));
   bg->rrbuf.ensure((size_t)nrhs * sizeof(double) + 16);
+  bg->stopbuf.ensure((size_t)bg->nb * nrhs * 2 * sizeof(double));
   if (relayout) {
     // the zero sites sit at other byte offsets in another precision or nrhs:
     // clear the buffers once so that they hold zeros again
@@ -624,6 +650,14 @@ void ensure_block_vecs(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs) {
       if (v->norm.p) HIPCHK(hipMemset(v->norm.p, 0, v->norm.bytes));
     }
     HIPCHK(hipDeviceSynchronize());  // as in DBuf::ensure: the null stream orders nothing else
+  }
+  const std::vector<void *> after = {bg->x.data.p, bg->x.norm.p, bg->r.data.p, bg->r.norm.p, bg->p.data.p,
+                                     bg->p.norm.p, bg->Ap.data.p, bg->Ap.norm.p, bg->o1v.data.p, bg->o1v.norm.p,
+                                     bg->e2v.data.p, bg->e2v.norm.p, bg->partial.p, bg->scal.p, bg->rrbuf.p,
+                                     bg->stopbuf.p};
+  if (relayout || before != after) {
+    drop_block_graphs(h, bg);
+    ++bg->gen;
   }
   bg->vprec = prec;
   bg->vnrhs = nrhs;
@@ -647,29 +681,37 @@ HopArgs block_hop_args(mspcg_handle *h, int nrhs, int nsites, const int *site_cb
   return a;
 }
 
-// out = A_s in for every block at once on the halo-extended domains
-// (B_e -> O1 -> E2 -> O1 -> B_e); optional partial Re<in, out> per workgroup.
-int block_hops(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, const Vec &in, const Vec &out, double *partial,
-               hipStream_t st) {
-  HopArgs a1 = block_hop_args(h, nrhs, bg->o1_tot, bg->d_o1_cb.as<int>(), bg->d_o1_nbr_be.as<int>(), in,
-                              bg->o1v.v, 1, prec);
-  a1.scale = -0.5;
-  a1.mat = h->x1.ptr(prec);
-  run_hop(h, 1, prec, 0, 1, EPI_DENSE, 0, 0, a1, st);
-  HopArgs a2 = block_hop_args(h, nrhs, bg->e2_tot, bg->d_e2_cb.as<int>(), bg->d_e2_nbr.as<int>(), bg->o1v.v,
-                              bg->e2v.v, 0, prec);
-  a2.scale = 0.5;
-  a2.other = in.data;
-  a2.other_norm = in.norm;
-  a2.other_stride = in.stride;
-  a2.other_idx = bg->d_e2_be.as<int>();
-  a2.other_zero = bg->be_tot;
-  run_hop(h, 2, prec, 0, 0, EPI_M5_OTHER, 0, 0, a2, st);
-  HopArgs a3 = block_hop_args(h, nrhs, bg->o1_tot, bg->d_o1_cb.as<int>(), bg->d_o1_nbr_e2.as<int>(), bg->e2v.v,
-                              bg->o1v.v, 1, prec);
-  a3.scale = -0.5;
-  a3.mat = h->x3.ptr(prec);
-  run_hop(h, 3, prec, 1, 0, EPI_DENSE, 0, 0, a3, st);
+// One of the four hops of A_s on the halo-extended domains, for every block at
+// once: 1: B_e -> O1, 2: O1 -> E2, 3: E2 -> O1, 4: O1 -> B_e (optional partial
+// Re<in, out> per workgroup).  Returns the grid size of the launch.
+int block_hop(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int which, const Vec &in, const Vec &out,
+              double *partial, hipStream_t st) {
+  if (which == 1) {  // c = M_phi M_5^{-1} (-1/2 H M_phi in) on O1
+    HopArgs a1 = block_hop_args(h, nrhs, bg->o1_tot, bg->d_o1_cb.as<int>(), bg->d_o1_nbr_be.as<int>(), in,
+                                bg->o1v.v, 1, prec);
+    a1.scale = -0.5;
+    a1.mat = h->x1.ptr(prec);
+    return run_hop(h, 1, prec, 0, 1, EPI_DENSE, 0, 0, a1, st);
+  }
+  if (which == 2) {  // y = M_5 in + 1/2 H c on E2
+    HopArgs a2 = block_hop_args(h, nrhs, bg->e2_tot, bg->d_e2_cb.as<int>(), bg->d_e2_nbr.as<int>(), bg->o1v.v,
+                                bg->e2v.v, 0, prec);
+    a2.scale = 0.5;
+    a2.other = in.data;
+    a2.other_norm = in.norm;
+    a2.other_stride = in.stride;
+    a2.other_idx = bg->d_e2_be.as<int>();
+    a2.other_zero = bg->be_tot;
+    return run_hop(h, 2, prec, 0, 0, EPI_M5_OTHER, 0, 0, a2, st);
+  }
+  if (which == 3) {  // f = M_5^{-+} M_phi^+ (-1/2 H^+ y) on O1
+    HopArgs a3 = block_hop_args(h, nrhs, bg->o1_tot, bg->d_o1_cb.as<int>(), bg->d_o1_nbr_e2.as<int>(), bg->e2v.v,
+                                bg->o1v.v, 1, prec);
+    a3.scale = -0.5;
+    a3.mat = h->x3.ptr(prec);
+    return run_hop(h, 3, prec, 1, 0, EPI_DENSE, 0, 0, a3, st);
+  }
+  // out = M_5^+ y + 1/2 M_phi^+ H^+ f on B_e
   HopArgs a4 = block_hop_args(h, nrhs, bg->be_tot, bg->d_be_cb.as<int>(), bg->d_be_nbr.as<int>(), bg->o1v.v, out,
                               0, prec);
   a4.scale = 0.5;
@@ -684,7 +726,15 @@ int block_hops(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, const Vec &in
     a4.dotw_norm = in.norm;
     a4.dotw_stride = in.stride;
   }
-  const int grid = run_hop(h, 4, prec, 1, 0, EPI_M5DAG_MPHIDAG, partial ? 1 : 0, 0, a4, st);
+  return run_hop(h, 4, prec, 1, 0, EPI_M5DAG_MPHIDAG, partial ? 1 : 0, 0, a4, st);
+}
+
+// out = A_s in for every block at once on the halo-extended domains
+// (B_e -> O1 -> E2 -> O1 -> B_e); optional partial Re<in, out> per workgroup.
+int block_hops(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, const Vec &in, const Vec &out, double *partial,
+               hipStream_t st) {
+  for (int which = 1; which <= 3; ++which) block_hop(h, bg, prec, nrhs, which, in, out, nullptr, st);
+  const int grid = block_hop(h, bg, prec, nrhs, 4, in, out, partial, st);
   return (bg->be_tot + grid - 1) / grid;  // sites per workgroup of the last hop
 }
 
@@ -715,11 +765,7 @@ void run_block_cg(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int k, dou
   double *scal = bg->scal.as<double>();
   // inner_tol > 0: precision-based stopping (inner_stop.hip), else exactly k iterations
   const bool stop = inner_tol > 0.0;
-  double *stopd = nullptr;
-  if (stop) {
-    bg->stopbuf.ensure((size_t)bg->nb * nrhs * 2 * sizeof(double));
-    stopd = bg->stopbuf.as<double>();
-  }
+  double *stopd = stop ? bg->stopbuf.as<double>() : nullptr;
   HIPCHK(block_gather(prec, ba, bg->x.v, bg->r.v, bg->p.v, r, rr, n_total, part, st));
   HIPCHK(block_scalars(2, ba, part, scal, st));
   if (stop) HIPCHK(inner_stop(0, bg->nb, nrhs, inner_tol, scal, stopd, st));
@@ -768,8 +814,48 @@ void more_sweeps(mspcg_handle *h, int nrhs, int sweeps, const Vec &z, const Vec 
 
 // ------------------------------------------------------------- solvers
 struct SolverWork {
-  double *rho, *pap, *alpha, *beta, *rr, *bb, *tmp, *rrt, *zrt;
+  double *rho, *pap, *alpha, *beta, *rr, *bb, *tmp, *rrt, *zrt, *zq;
   int *active;
+};
+
+// Time split of a solve: an event is recorded on the solver's stream at each
+// phase boundary, tagged with the phase that starts there; the time of a phase
+// is the elapsed time to the next event.  Completed intervals are summed at
+// the solver's host synchronisations and their events recycled.
+struct PhaseTimer {
+  enum { OP = 0, PRECOND = 1, BLAS = 2 };
+  bool on = false;
+  hipStream_t st = nullptr;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<hipEvent_t, int>> marks;
+  double t[3] = {0, 0, 0};
+  void mark(int phase) {
+    if (!on) return;
+    hipEvent_t e;
+    if (pool.empty()) {
+      HIPCHK(hipEventCreate(&e));
+    } else {
+      e = pool.back();
+      pool.pop_back();
+    }
+    HIPCHK(hipEventRecord(e, st));
+    marks.emplace_back(e, phase);
+  }
+  // after a synchronisation of the stream: every interval but the open last one is complete
+  void drain() {
+    if (!on || marks.size() < 2) return;
+    for (size_t i = 0; i + 1 < marks.size(); ++i) {
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, marks[i].first, marks[i + 1].first));
+      t[marks[i].second] += 1e-3 * ms;
+      pool.push_back(marks[i].first);
+    }
+    marks.erase(marks.begin(), marks.end() - 1);
+  }
+  ~PhaseTimer() {
+    for (auto &m : marks) (void)hipEventDestroy(m.first);
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
 };
 
 mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const mspcg_solver *s,
@@ -803,7 +889,7 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
     if (pc) h->sz.ensure(MSPCG_F64, nrhs, h->Vh, Ls);
     const size_t nparts_max = std::max<size_t>((size_t)std::max(h->Vh, kBlasGrid), bg ? (size_t)bg->be_tot : 0);
     h->partial.ensure(nparts_max * nrhs * sizeof(double));
-    h->scal.ensure((size_t)nrhs * 10 * sizeof(double) + 64);
+    h->scal.ensure((size_t)nrhs * 11 * sizeof(double) + 64);
     double *part = h->partial.as<double>();
     SolverWork w;
     w.rho = h->scal.as<double>();
@@ -815,7 +901,12 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
     w.tmp = w.bb + nrhs;
     w.rrt = w.tmp + nrhs;
     w.zrt = w.rrt + nrhs;
-    w.active = reinterpret_cast<int *>(w.zrt + nrhs);
+    w.zq = w.zrt + nrhs;
+    w.active = reinterpret_cast<int *>(w.zq + nrhs);
+    PhaseTimer tm;
+    tm.on = s->timing != 0;
+    tm.st = st;
+    tm.mark(PhaseTimer::BLAS);
     Vec X = vec_of(h, x), B = vec_of(h, b), R = h->sr.v, P = h->sp.v, Q = h->sq.v;
     Vec Z = pc ? h->sz.v : R;
     double *xd = (double *)X.data, *bd = (double *)B.data, *rd = (double *)R.data, *pd = (double *)P.data,
@@ -829,6 +920,7 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
     auto to_host = [&](const double *d, std::vector<double> &hv) {
       HIPCHK(hipMemcpyAsync(hv.data(), d, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
+      tm.drain();
       for (double v : hv)
         if (!std::isfinite(v)) fail(MSPCG_ENONFINITE, "non-finite value in a solver reduction");
     };
@@ -836,7 +928,9 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
       HIPCHK(hipMemcpyAsync(w.active, active.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
     };
     auto true_residual = [&] {  // r = b - A x, rr
+      tm.mark(PhaseTimer::OP);
       apply_mdagm(h, MSPCG_F64, nrhs, Q, X, h->tmp_o.v, h->tmp_e.v, nullptr, st);
+      tm.mark(PhaseTimer::BLAS);
       HIPCHK(blas_axpby(rd, 1.0, bd, -1.0, qd, n, nrhs, st));
       norm2(rd, w.rr);
       to_host(w.rr, hr);
@@ -852,11 +946,15 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
         precond_launch();
         return;
       }
+      // size (and, for another precision or nrhs, clear) the block buffers before
+      // the key is formed: the key names their generation
+      ensure_links(h, pc->inner_prec, st);
+      ensure_block_vecs(h, bg, pc->inner_prec, nrhs);
       int64_t tol_bits;
       std::memcpy(&tol_bits, &pc->inner_tol, sizeof tol_bits);
-      const std::vector<intptr_t> key = {(intptr_t)bg, pc->inner_prec, nrhs, pc->n_inner, (intptr_t)tol_bits,
-                                         (intptr_t)Zv.data, (intptr_t)Rv.data, (intptr_t)rrv, (intptr_t)part,
-                                         (intptr_t)zrv};
+      const std::vector<intptr_t> key = {(intptr_t)bg, (intptr_t)bg->gen, pc->inner_prec, nrhs, pc->n_inner,
+                                         (intptr_t)tol_bits, (intptr_t)Zv.data, (intptr_t)Rv.data, (intptr_t)rrv,
+                                         (intptr_t)part, (intptr_t)zrv};
       auto it = h->graphs.find(key);
       if (it != h->graphs.end()) {
         HIPCHK(hipGraphLaunch(it->second, st));
@@ -886,6 +984,7 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
         HIPCHK(hipMemcpyAsync(w.tmp, w.rr, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
         return;
       }
+      tm.mark(PhaseTimer::PRECOND);
       precond_one(Z, R, w.rr, w.tmp);
       if (pc->n_sweeps > 1) {
         more_sweeps(h, nrhs, pc->n_sweeps, Z, R, w.rrt, part, st,
@@ -893,6 +992,7 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
         HIPCHK(blas_dot_partial(zd, rd, n, nrhs, part, st));
         HIPCHK(blas_reduce(part, kBlasGrid, nrhs, w.tmp, st));
       }
+      tm.mark(PhaseTimer::BLAS);
     };
     const double tol2 = s->tol * s->tol;
     norm2(bd, w.bb);
@@ -916,7 +1016,9 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
       HIPCHK(blas_axpby(pd, 1.0, zd, 0.0, zd, n, nrhs, st));  // p = z
       HIPCHK(hipMemcpyAsync(w.rho, w.tmp, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
       while (it < s->max_iter) {
+        tm.mark(PhaseTimer::OP);
         const int hop_parts = apply_mdagm(h, MSPCG_F64, nrhs, Q, P, h->tmp_o.v, h->tmp_e.v, part, st);
+        tm.mark(PhaseTimer::BLAS);
         HIPCHK(blas_reduce(part, hop_parts, nrhs, w.pap, st));
         HIPCHK(solver_scalars(0, nrhs, w.active, w.rho, w.pap, w.alpha, st));
         HIPCHK(blas_update_xr(xd, rd, pd, qd, w.alpha, n, nrhs, part, st));
@@ -945,12 +1047,21 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
         if (!any) break;
         precond();
         if (pc) inner += (long long)pc->n_inner * std::max(1, pc->n_sweeps);
-        HIPCHK(solver_scalars(1, nrhs, w.active, w.rho, w.tmp, w.beta, st));
+        if (s->flexible_beta) {
+          // Polak-Ribiere: beta = <z', r' - r> / <z, r> with r' - r = -alpha A p
+          // (q still holds A p), i.e. beta = -<z', A p> / <p, A p>
+          HIPCHK(blas_dot_partial(zd, qd, n, nrhs, part, st));
+          HIPCHK(blas_reduce(part, kBlasGrid, nrhs, w.zq, st));
+          HIPCHK(solver_scalars(2, nrhs, w.active, w.rho, w.tmp, w.beta, st, w.zq, w.pap));
+        } else {
+          HIPCHK(solver_scalars(1, nrhs, w.active, w.rho, w.tmp, w.beta, st));
+        }
         HIPCHK(blas_xpay(pd, zd, w.beta, n, nrhs, st));
       }
     }
     // final true residual
     true_residual();
+    tm.mark(PhaseTimer::BLAS);
     bool conv = true;
     for (int i = 0; i < nrhs; ++i) {
       const double rel = hb[i] > 0 ? std::sqrt(hr[i] / hb[i]) : 0.0;
@@ -958,11 +1069,14 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
       if (st_out && st_out->true_rel_resid) st_out->true_rel_resid[i] = rel;
     }
     HIPCHK(hipStreamSynchronize(st));
+    tm.drain();
     if (st_out) {
       st_out->outer_iters = it;
       st_out->inner_iters = inner;
       st_out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-      st_out->t_precond = 0;
+      st_out->t_outer_op = tm.t[PhaseTimer::OP];
+      st_out->t_precond = tm.t[PhaseTimer::PRECOND];
+      st_out->t_blas = tm.t[PhaseTimer::BLAS];
     }
     result = conv ? MSPCG_OK : MSPCG_NOT_CONVERGED;
   });
@@ -1156,9 +1270,11 @@ mspcg_status local_block_cg(mspcg_handle *h, mspcg_field *z, const mspcg_field *
     if (!h || !pc) fail(MSPCG_EINVAL, "NULL handle or preconditioner");
     check_field(h, z, "z");
     check_field(h, r, "r");
-    if (z->prec != MSPCG_F64 || r->prec != MSPCG_F64) fail(MSPCG_EUNSUPPORTED, "local_block_cg takes F64 r and z");
+    if (z->prec != r->prec) fail(MSPCG_EINVAL, "local_block_cg: r and z differ in precision");
+    if (z->prec != MSPCG_F64 && z->prec != MSPCG_F32) fail(MSPCG_EUNSUPPORTED, "local_block_cg takes F64 or F32 r and z");
     if (z->parity != 0 || r->parity != 0) fail(MSPCG_EINVAL, "local_block_cg works on even sites");
     if (z->nrhs != r->nrhs) fail(MSPCG_EINVAL, "nrhs mismatch");
+    if (z->data == r->data) fail(MSPCG_EINVAL, "local_block_cg: z must not alias r");
     if (pc->n_inner < 0) fail(MSPCG_EINVAL, "n_inner < 0");
     if (pc->inner_prec < MSPCG_F64 || pc->inner_prec > MSPCG_BF16) fail(MSPCG_EINVAL, "bad inner precision");
     if (!(pc->inner_tol >= 0.0) || !std::isfinite(pc->inner_tol)) fail(MSPCG_EINVAL, "inner_tol < 0 or not finite");
@@ -1169,19 +1285,29 @@ mspcg_status local_block_cg(mspcg_handle *h, mspcg_field *z, const mspcg_field *
     const long long n = (long long)h->Vh * h->par.Ls * 24;
     ensure_block_vecs(h, bg, pc->inner_prec, nrhs);
     h->partial.ensure((size_t)std::max(kBlasGrid, bg->be_tot) * nrhs * sizeof(double));
+    // F32 boundary fields: the preconditioner works on F64 copies
+    Vec Zv = vec_of(h, z), Rv = vec_of(h, r);
+    if (r->prec == MSPCG_F32) {
+      h->lbc_r.ensure(MSPCG_F64, nrhs, h->Vh, h->par.Ls);
+      h->lbc_z.ensure(MSPCG_F64, nrhs, h->Vh, h->par.Ls);
+      HIPCHK(launch_convert(h->lbc_r.v, Rv, nrhs, (long long)h->Vh * h->par.Ls, h->par.Ls, st));
+      Rv = h->lbc_r.v;
+      Zv = h->lbc_z.v;
+    }
     double *rr = bg->rrbuf.as<double>();
-    HIPCHK(blas_dot_partial((const double *)r->data, (const double *)r->data, n, nrhs, h->partial.as<double>(), st));
+    HIPCHK(blas_dot_partial((const double *)Rv.data, (const double *)Rv.data, n, nrhs, h->partial.as<double>(), st));
     HIPCHK(blas_reduce(h->partial.as<double>(), kBlasGrid, nrhs, rr, st));
-    run_block_cg(h, bg, pc->inner_prec, nrhs, pc->n_inner, pc->inner_tol, vec_of(h, z), vec_of(h, r), rr, nullptr,
-                 nullptr, st);
+    run_block_cg(h, bg, pc->inner_prec, nrhs, pc->n_inner, pc->inner_tol, Zv, Rv, rr, nullptr, nullptr, st);
     if (pc->n_sweeps > 1) {
-      h->scal.ensure((size_t)nrhs * 10 * sizeof(double) + 64);
-      more_sweeps(h, nrhs, pc->n_sweeps, vec_of(h, z), vec_of(h, r), h->scal.as<double>(), h->partial.as<double>(), st,
+      h->scal.ensure((size_t)nrhs * 11 * sizeof(double) + 64);
+      more_sweeps(h, nrhs, pc->n_sweeps, Zv, Rv, h->scal.as<double>(), h->partial.as<double>(), st,
                   [&](const Vec &z2, const Vec &t, double *rrt) {
                     run_block_cg(h, bg, pc->inner_prec, nrhs, pc->n_inner, pc->inner_tol, z2, t, rrt, nullptr,
                                  nullptr, st);
                   });
     }
+    if (z->prec == MSPCG_F32)
+      HIPCHK(launch_convert(vec_of(h, z), Zv, nrhs, (long long)h->Vh * h->par.Ls, h->par.Ls, st));
   });
 }
 
@@ -1322,6 +1448,31 @@ mspcg_status mspcg_block_apply(mspcg_handle *h, mspcg_field *out, const mspcg_fi
     HIPCHK(block_gather(prec, ba, bg->x.v, bg->r.v, bg->p.v, vec_of(h, in), nullptr, n_total, part, st));
     (void)block_hops(h, bg, prec, nrhs, bg->p.v, bg->Ap.v, nullptr, st);
     HIPCHK(block_scatter(prec, ba, vec_of(h, out), bg->Ap.v, Vec(), nullptr, n_total, part, st));
+  });
+}
+
+mspcg_status mspcg_debug_block_hop(mspcg_handle *h, const mspcg_precond *pc, int nrhs, int hop, int reps,
+                                   long long sites[2], void *stream) {
+  return guarded([&] {
+    if (!h || !pc) fail(MSPCG_EINVAL, "NULL argument");
+    if (hop < 1 || hop > 4 || reps < 0) fail(MSPCG_EINVAL, "hop must be 1..4 and reps >= 0");
+    if (nrhs < 1 || nrhs > MSPCG_MAX_NRHS) fail(MSPCG_EINVAL, "bad nrhs");
+    const int prec = pc->inner_prec;
+    if (prec < MSPCG_F64 || prec > MSPCG_BF16) fail(MSPCG_EINVAL, "bad precision");
+    if (hop_threads(h->par.Ls, nrhs, 1) > 256) fail(MSPCG_EUNSUPPORTED, "nrhs x Ls above one workgroup");
+    hipStream_t st = S(stream);
+    BlockGeom *bg = get_blocks(h, pc->nblk, pc->no_snake, st);
+    ensure_links(h, prec, st);
+    ensure_block_vecs(h, bg, prec, nrhs);
+    double *part = bg->partial.as<double>();
+    for (int i = 0; i < reps; ++i) block_hop(h, bg, prec, nrhs, hop, bg->p.v, bg->Ap.v, hop == 4 ? part : nullptr, st);
+    if (sites) {
+      // input and output domains: 1: B_e -> O1, 2: O1 -> E2, 3: E2 -> O1, 4: O1 -> B_e
+      long long nbe = 0, no1 = 0, ne2 = 0;
+      for (int b = 0; b < bg->nb; ++b) nbe += bg->be_n[b], no1 += bg->o1_n[b], ne2 += bg->e2_n[b];
+      sites[0] = hop == 1 ? nbe : hop == 3 ? ne2 : no1;
+      sites[1] = hop == 2 ? ne2 : hop == 4 ? nbe : no1;
+    }
   });
 }
 

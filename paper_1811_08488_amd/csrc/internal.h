@@ -97,10 +97,12 @@ hipError_t blas_xpay(double *p, const double *z, const double *beta, long long n
 hipError_t blas_axpby(double *out, double a, const double *x, double b, const double *y, long long n, int nrhs,
                       hipStream_t st);
 // Solver scalars per right-hand side (all device arrays [nrhs]):
-//   mode 0: alpha = active ? rho / pap : 0
-//   mode 1: beta = active ? rho_new / rho : 0; rho = rho_new
+//   mode 0: alpha = active ? rho / pap : 0                       (x1 = pap)
+//   mode 1: beta = active ? rho_new / rho : 0; rho = rho_new     (x1 = rho_new; Fletcher-Reeves)
+//   mode 2: beta = active ? -zq / pap : 0; rho = rho_new         (x1 = rho_new, x2 = <z', A p>, x3 = <p, A p>;
+//           Polak-Ribiere, <z', r' - r> / <z, r> with r' - r = -alpha A p)
 hipError_t solver_scalars(int mode, int nrhs, const int *active, double *rho, const double *x1, double *out,
-                          hipStream_t st);
+                          hipStream_t st, const double *x2 = nullptr, const double *x3 = nullptr);
 
 // ------------------------------------------------------------- block preconditioner
 struct BlockArgs {

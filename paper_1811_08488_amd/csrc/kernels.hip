@@ -17,6 +17,16 @@
 namespace mspcg {
 
 // ---------------------------------------------------------------- helpers
+// Orders a wave's LDS stores before its following LDS loads of words other
+// lanes of the same wave stored: wavefront-scope release/acquire fences (the
+// compiler neither moves nor forwards memory accesses across them) around a
+// wave barrier.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename R>
 __device__ inline void zero24(R v[24]) {
 #pragma unroll
@@ -390,8 +400,10 @@ __device__ inline void dense_chiral(R *lds, const R *X, int nthr, int tid, int s
 // The same contraction where every wave holds whole (site, rhs) groups (the
 // DPP and ds_bpermute layouts: G groups of Ls lanes per wave): each wave
 // contracts only its own groups' columns, in its own slice of the LDS
-// structure of arrays, so no workgroup barrier is needed (a wave's LDS
-// accesses are served in order).  Per chirality the wave's 12 G columns
+// structure of arrays, so no workgroup barrier is needed.  Lanes read words
+// that other lanes of the same wave wrote: wave_lds_sync between the stores
+// and those loads keeps the compiler from moving one across the other (the
+// hardware serves one wave's LDS accesses in order).  Per chirality the wave's 12 G columns
 // form ceil(12 G / 16) MFMA tiles; the X operand of a lane is the same for
 // every tile and is read once.  Needs Ls % 4 == 0 and Ls <= 32; X must be
 // visible to all waves (staged before a barrier).  LSC > 0 fixes Ls at
@@ -405,6 +417,7 @@ __device__ inline void dense_chiral_wave_t(R *lds, const R *X, int nthr, int tid
   R *W = lds + (tid - lane);  // component k of the wave's lane j: W[k * nthr + j]
 #pragma unroll
   for (int k = 0; k < 24; ++k) W[k * nthr + lane] = v[k];
+  wave_lds_sync();
   const int row = lane & 15, kq = lane >> 4;
   const int ncol = 12 * G, ntn = (ncol + 15) >> 4, nk = Ls >> 2;
 #pragma unroll
@@ -439,6 +452,7 @@ __device__ inline void dense_chiral_wave_t(R *lds, const R *X, int nthr, int tid
           if (Ls > 16 && 16 + m < Ls) Wc[16 + m] = scale * c1[i];
         }
       }
+      wave_lds_sync();
     }
   }
 #pragma unroll
@@ -970,23 +984,29 @@ hipError_t blas_axpby(double *out, double a, const double *x, double b, const do
   return hipGetLastError();
 }
 
-__global__ void k_solver_scalars(int mode, int nrhs, const int *active, double *rho, const double *x1, double *out) {
+__global__ void k_solver_scalars(int mode, int nrhs, const int *active, double *rho, const double *x1, double *out,
+                                 const double *x2, const double *x3) {
   const int r = threadIdx.x;
   if (r >= nrhs) return;
   const bool on = active[r] != 0;
   if (mode == 0) {
     const double pap = x1[r];
     out[r] = (on && pap != 0.0) ? rho[r] / pap : 0.0;
-  } else {
+  } else if (mode == 1) {
     const double rn = x1[r];
     out[r] = (on && rho[r] != 0.0) ? rn / rho[r] : 0.0;
+    if (on) rho[r] = rn;
+  } else {
+    const double rn = x1[r], zq = x2[r], pap = x3[r];
+    out[r] = (on && pap != 0.0) ? -zq / pap : 0.0;
     if (on) rho[r] = rn;
   }
 }
 
 hipError_t solver_scalars(int mode, int nrhs, const int *active, double *rho, const double *x1, double *out,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(k_solver_scalars, dim3(1), dim3(64), 0, st, mode, nrhs, active, rho, x1, out);
+                          hipStream_t st, const double *x2, const double *x3) {
+  if (mode == 2 && (!x2 || !x3)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_solver_scalars, dim3(1), dim3(64), 0, st, mode, nrhs, active, rho, x1, out, x2, x3);
   return hipGetLastError();
 }
 

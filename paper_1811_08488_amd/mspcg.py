@@ -23,7 +23,7 @@ MAX_LS, MAX_NRHS = 32, 16
 EXPORTED = [
     "mspcg_create", "mspcg_destroy", "dslash_eo", "m5inv", "mdagm", "local_block_cg", "cg_solve", "mspcg_solve",
     "dwf_prepare_rhs", "dwf_reconstruct", "mspcg_debug_site_maps", "mspcg_debug_block_sites", "mspcg_convert",
-    "mspcg_block_apply", "mspcg_last_error",
+    "mspcg_block_apply", "mspcg_debug_block_hop", "mspcg_last_error",
 ]
 
 
@@ -44,13 +44,13 @@ class Precond(ctypes.Structure):
 
 class Solver(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("reliable_interval", ctypes.c_int),
-                ("use_graph", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("timing", ctypes.c_int), ("flexible_beta", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("outer_iters", ctypes.c_int), ("inner_iters", ctypes.c_longlong),
                 ("true_rel_resid", ctypes.POINTER(ctypes.c_double)), ("seconds", ctypes.c_double),
-                ("t_precond", ctypes.c_double)]
+                ("t_outer_op", ctypes.c_double), ("t_precond", ctypes.c_double), ("t_blas", ctypes.c_double)]
 
 
 _lib = None
@@ -80,6 +80,7 @@ def lib():
             "mspcg_debug_block_sites": [P, P, I, P, P, P, P],
             "mspcg_convert": [P, FP, FP, P],
             "mspcg_block_apply": [P, FP, FP, ctypes.POINTER(Precond), P],
+            "mspcg_debug_block_hop": [P, ctypes.POINTER(Precond), I, I, I, P, P],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -258,6 +259,15 @@ class Handle:
         _check(lib().mspcg_block_apply(self.h, ctypes.byref(out.c()), ctypes.byref(inp.c()), ctypes.byref(pc),
                                        _stream(stream)))
 
+    def block_hop(self, nblk, prec, nrhs, hop, reps=1, stream=None, no_snake=0):
+        """Launch block hop 1..4 of the inner iteration `reps` times; returns the 4D sites of its
+        (input, output) domains summed over blocks."""
+        pc = Precond((ctypes.c_int * 4)(*nblk), 0, int(prec), int(no_snake), 0.0, 1)
+        n = (ctypes.c_longlong * 2)()
+        _check(lib().mspcg_debug_block_hop(self.h, ctypes.byref(pc), int(nrhs), int(hop), int(reps), n,
+                                           _stream(stream)))
+        return int(n[0]), int(n[1])
+
     def local_block_cg(self, z: Field, r: Field, nblk, n_inner, inner_prec=F32, stream=None, no_snake=0,
                        inner_tol=0.0, n_sweeps=1):
         pc = Precond((ctypes.c_int * 4)(*nblk), int(n_inner), int(inner_prec), int(no_snake), float(inner_tol),
@@ -274,10 +284,10 @@ class Handle:
                                      ctypes.byref(phi_o.c()), _stream(stream)))
 
     # -------------------------------------------------------- solvers
-    def _solve(self, x: Field, b: Field, tol, max_iter, reliable, precond, use_graph=1):
+    def _solve(self, x: Field, b: Field, tol, max_iter, reliable, precond, use_graph=1, timing=0, flexible_beta=0):
         resid = (ctypes.c_double * b.nrhs)()
-        st = Stats(0, 0, ctypes.cast(resid, ctypes.POINTER(ctypes.c_double)), 0.0, 0.0)
-        s = Solver(float(tol), int(max_iter), int(reliable), int(use_graph))
+        st = Stats(0, 0, ctypes.cast(resid, ctypes.POINTER(ctypes.c_double)), 0.0, 0.0, 0.0, 0.0)
+        s = Solver(float(tol), int(max_iter), int(reliable), int(use_graph), int(timing), int(flexible_beta))
         if precond is None:
             rc = lib().cg_solve(self.h, ctypes.byref(x.c()), ctypes.byref(b.c()), ctypes.byref(s), ctypes.byref(st))
         else:
@@ -288,15 +298,17 @@ class Handle:
                                    ctypes.byref(pc), ctypes.byref(st))
         _check(rc, allow=(OK, NOT_CONVERGED))
         return {"status": rc, "outer_iters": st.outer_iters, "inner_iters": st.inner_iters,
-                "true_rel_resid": list(resid), "seconds": st.seconds}
+                "true_rel_resid": list(resid), "seconds": st.seconds, "t_outer_op": st.t_outer_op,
+                "t_precond": st.t_precond, "t_blas": st.t_blas}
 
-    def cg_solve(self, x: Field, b: Field, tol=1e-10, max_iter=10000, reliable=50):
-        return self._solve(x, b, tol, max_iter, reliable, None)
+    def cg_solve(self, x: Field, b: Field, tol=1e-10, max_iter=10000, reliable=50, timing=0):
+        return self._solve(x, b, tol, max_iter, reliable, None, timing=timing)
 
     def mspcg_solve(self, x: Field, b: Field, nblk, n_inner, inner_prec=F32, tol=1e-10, max_iter=10000,
-                    reliable=50, use_graph=1, no_snake=0, inner_tol=0.0, n_sweeps=1):
+                    reliable=50, use_graph=1, no_snake=0, inner_tol=0.0, n_sweeps=1, timing=0, flexible_beta=0):
         return self._solve(x, b, tol, max_iter, reliable,
-                           (nblk, n_inner, inner_prec, no_snake, inner_tol, n_sweeps), use_graph)
+                           (nblk, n_inner, inner_prec, no_snake, inner_tol, n_sweeps), use_graph, timing,
+                           flexible_beta)
 
     # -------------------------------------------------------- debug exports
     def site_maps(self, parity):

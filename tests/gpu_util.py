@@ -24,7 +24,40 @@ def require_gpu():
 
 
 def rel(a, b):
+    """Relative 2-norm of the difference over the whole field."""
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def site_err(got, want, floor=1e-3):
+    """Largest element-wise error measured against the norm of its own 5D site:
+    max over (rhs, site, s, spin, colour) of |got - want| / ||want_site||, a
+    5D site being the 12 complex values of one (rhs, cb, s).  Sites whose norm
+    is below `floor` times the field's RMS site norm are measured against that
+    floor.  A single wrong spin-colour component anywhere fails it, unlike a
+    norm over the whole field."""
+    g = np.asarray(got).reshape(-1, 12)
+    w = np.asarray(want).reshape(-1, 12)
+    n = np.linalg.norm(w, axis=1)
+    ref = np.maximum(n, floor * np.sqrt(np.mean(n * n)))
+    if not np.all(ref > 0):
+        return float(np.max(np.abs(g - w)))
+    return float(np.max(np.abs(g - w) / ref[:, None]))
+
+
+# Element-wise tolerances against the site norm, per application (one hop, one
+# M_5^-1): the stored output rounds each real to u * n with n <= ||site|| (u the
+# unit roundoff: FP32 2^-24, FP16 2^-11, BF16 2^-9), and the links stored in
+# the same type add about u per product; the F16 hop also rounds its projected
+# half spinor (2^-11).  Both are compared with the oracle applied to the
+# rounded input the GPU received.
+SITE_TOL = {M.F64: 1e-13, M.F32: 1e-6, M.F16: 5e-3, M.BF16: 5e-3}
+
+
+def rounded(h, x, parity, prec):
+    """The values a field of `prec` holds after an upload of x (what the kernels read)."""
+    if prec == M.F64:
+        return np.asarray(x)
+    return h.download(h.upload(x, parity, prec))
 
 
 class Setup:

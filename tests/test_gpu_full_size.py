@@ -5,7 +5,10 @@ sites, halo-extended block domains).  The oracle recomputes each sampled output
 on a small periodic window cut around the site (tests/embedding.py).
 
 Tolerances are the per-application ones: FP64 1e-13, FP32 1e-6, FP16/BF16 with
-per-site norm 5e-3 (relative 2-norm over all sampled outputs).
+per-site norm 5e-3, as a relative 2-norm over all sampled outputs against the
+oracle on the FP64 input and, for the single-hop and fifth-dimension
+operators, element by element against each sampled 5D site's norm against
+the oracle on the rounded input the kernels read.
 """
 from types import SimpleNamespace
 
@@ -16,7 +19,7 @@ import oracle as O
 from paper_1811_08488_amd import mspcg as M
 from paper_1811_08488_amd.workloads import WORKLOADS
 from tests import embedding as E
-from tests.gpu_util import PNAME, TOL, rel, require_gpu
+from tests.gpu_util import PNAME, SITE_TOL, TOL, rel, require_gpu, site_err
 
 pytestmark = pytest.mark.gpu
 
@@ -85,6 +88,11 @@ def gpu_input(S, cb, vals, parity, prec):
     return g
 
 
+def rounded_vals(S, f, cb):
+    """The input values a field holds at the sparse sites cb, as [n, nrhs, Ls, 4, 3]."""
+    return S.h.read_sites(f, cb).transpose(1, 0, 2, 3, 4)
+
+
 def oracle_at(S, x, R, in_parity, cb, vals, fn, pins=None):
     """[nrhs, Ls, 4, 3]: fn(sub_action, sub_links, sub_input, window) at x on its window."""
     w = S.w
@@ -101,19 +109,26 @@ def cb_of(L, pts):
     return np.array([int(E.lex_of(L, p)) >> 1 for p in pts])
 
 
-@pytest.mark.parametrize("prec", [M.F64, M.F32, M.F16], ids=lambda p: PNAME[p])
+@pytest.mark.parametrize("prec", [M.F64, M.F32, M.F16, M.BF16], ids=lambda p: PNAME[p])
 @pytest.mark.parametrize("dagger", [0, 1])
 def test_dslash_eo_sampled(W, prec, dagger):
     S = W
     for p in (0, 1):
         pts = S.samples[p]
         cb, vals = S.lat.sparse_input(pts, 1, 1 - p, S.w.Ls, S.w.nrhs)
+        fin = gpu_input(S, cb, vals, 1 - p, prec)
         out = S.h.field(prec, S.w.nrhs, p)
-        S.h.dslash_eo(out, gpu_input(S, cb, vals, 1 - p, prec), dagger)
+        S.h.dslash_eo(out, fin, dagger)
         got = S.h.read_sites(out, cb_of(S.w.L, pts))
-        want = np.stack([oracle_at(S, x, 1, 1 - p, cb, vals,
-                                   lambda A, U, psi, win: O.dslash_eo(A, U, psi, p, dagger)) for x in pts], axis=1)
+
+        def op(A, U, psi, win):
+            return O.dslash_eo(A, U, psi, p, dagger)
+
+        want = np.stack([oracle_at(S, x, 1, 1 - p, cb, vals, op) for x in pts], axis=1)
         assert rel(got, want) <= TOL[prec], (p, rel(got, want))
+        rv = rounded_vals(S, fin, cb)
+        want_r = np.stack([oracle_at(S, x, 1, 1 - p, cb, rv, op) for x in pts], axis=1)
+        assert site_err(got, want_r) <= SITE_TOL[prec], (p, site_err(got, want_r))
 
 
 @pytest.mark.parametrize("dagger", [0, 1])

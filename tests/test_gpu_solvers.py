@@ -6,7 +6,7 @@ import oracle as O
 from paper_1811_08488_amd import mspcg as M
 from paper_1811_08488_amd import synth
 from paper_1811_08488_amd.workloads import WORKLOADS
-from tests.gpu_util import PNAME, Setup, rel, require_gpu
+from tests.gpu_util import PNAME, Setup, rel, require_gpu, site_err
 
 pytestmark = pytest.mark.gpu
 
@@ -260,3 +260,94 @@ def test_graph_replay_matches_eager(S):
         out.setdefault(g, []).append((st["outer_iters"], S.h.download(fx)))
     assert out[0][0][0] == out[1][0][0] == out[1][1][0]
     assert np.array_equal(out[0][0][1], out[1][0][1]) and np.array_equal(out[1][0][1], out[1][1][1])
+
+
+def test_graph_cache_follows_block_buffers():
+    """A captured preconditioner bakes in the block work buffers, which another
+    inner precision or nrhs reallocates or clears: a solve after such a change
+    recaptures instead of replaying the old graph.  F16, F32, F16 solves with
+    two right-hand sides on one handle equal the F16 solve on a fresh handle
+    bit for bit (default launch shapes on both, so the sums are ordered alike)."""
+    require_gpu()
+    import os
+
+    L, Ls, nblk = SMALL
+    old = os.environ.get("MSPCG_AUTOTUNE")
+    os.environ["MSPCG_AUTOTUNE"] = "0"
+    try:
+        s1 = Setup(L, Ls, "mobius", mf=0.05, seed=8)
+        s2 = Setup(L, Ls, "mobius", mf=0.05, seed=8)
+    finally:
+        if old is None:
+            del os.environ["MSPCG_AUTOTUNE"]
+        else:
+            os.environ["MSPCG_AUTOTUNE"] = old
+    b = s1.rand(2, 120)
+
+    def solve(s, prec, k=3):
+        fx = s.h.field(M.F64, 2, 0)
+        st = s.h.mspcg_solve(fx, s.h.upload(b, 0), nblk, k, prec, tol=1e-10)
+        return st["outer_iters"], s.h.download(fx)
+
+    seq = [solve(s1, p) for p in (M.F16, M.F32, M.F16)]
+    # local_block_cg in between relayouts the buffers for F32 with one right-hand side
+    s1.h.local_block_cg(s1.h.field(M.F64, 1, 0), s1.h.upload(b[:1], 0), nblk, 3, M.F32)
+    seq.append(solve(s1, M.F16))
+    fresh = solve(s2, M.F16)
+    for it, x in (seq[2], seq[3]):
+        assert it == fresh[0] and np.array_equal(x, fresh[1])
+    assert seq[1][0] > 0 and not np.array_equal(seq[1][1], fresh[1])  # the F32 solve is a different run
+
+
+def test_local_block_cg_f32_fields(S):
+    """F32 boundary fields: the same preconditioner on widened copies."""
+    nblk = SMALL[2]
+    r = S.rand(2, 121)
+    z64 = S.h.field(M.F64, 2, 0)
+    S.h.local_block_cg(z64, S.h.upload(r, 0), nblk, 3, M.F32)
+    r32 = S.h.upload(r, 0, M.F32)
+    z32 = S.h.field(M.F32, 2, 0)
+    S.h.local_block_cg(z32, r32, nblk, 3, M.F32)
+    got, ref = S.h.download(z32), S.h.download(z64)
+    want = O.local_block_cg(S.oa, S.U, r[0], nblk, 3)
+    assert site_err(got[0], want) <= 2 * 3 * 1e-6 + 1e-6, site_err(got[0], want)
+    assert rel(got, ref) <= 1e-6
+    with pytest.raises(M.MspcgError) as e:
+        S.h.local_block_cg(S.h.field(M.F16, 1, 0), S.h.upload(r[:1], 0, M.F16), nblk, 3, M.F32)
+    assert e.value.status == M.EUNSUPPORTED
+
+
+def test_flexible_beta_matches_oracle(S):
+    """flexible_beta = 1 (Polak-Ribiere beta) against the oracle's variant."""
+    nblk = SMALL[2]
+    b = S.rand(1, 122)[0]
+    xo, st_o = O.solve(S.oa, S.U, b, nblk=nblk, k=3, tol=1e-10, maxiter=2000, flexible=True)
+    fx = S.h.field(M.F64, 1, 0)
+    st = S.h.mspcg_solve(fx, S.h.upload(b, 0), nblk, 3, M.F64, tol=1e-10, flexible_beta=1)
+    assert st["status"] == M.OK
+    x = S.h.download(fx)[0]
+    assert site_err(x, xo) <= 1e-7
+    assert abs(st["outer_iters"] - st_o.iters) <= 2 + 0.02 * st_o.iters
+    # and with FP16 inner storage it converges
+    fx = S.h.field(M.F64, 1, 0)
+    st = S.h.mspcg_solve(fx, S.h.upload(b, 0), nblk, 3, M.F16, tol=1e-10, flexible_beta=1)
+    assert st["status"] == M.OK and _true_resid(S, S.h.download(fx)[0], b) <= 1e-10
+
+
+def test_solver_time_split(S):
+    """timing = 1 fills the split of the solve time; the iterates do not change."""
+    nblk = SMALL[2]
+    b = S.h.upload(S.rand(1, 123), 0)
+    runs = {}
+    for timing in (0, 1):
+        fx = S.h.field(M.F64, 1, 0)
+        st = S.h.mspcg_solve(fx, b, nblk, 3, M.F16, tol=1e-10, timing=timing)
+        runs[timing] = (st, S.h.download(fx))
+    st0, st1 = runs[0][0], runs[1][0]
+    assert st0["t_outer_op"] == st0["t_precond"] == st0["t_blas"] == 0.0
+    assert st1["t_outer_op"] > 0 and st1["t_precond"] > 0 and st1["t_blas"] > 0
+    assert st1["t_outer_op"] + st1["t_precond"] + st1["t_blas"] <= st1["seconds"] * 1.02
+    assert st0["outer_iters"] == st1["outer_iters"] and np.array_equal(runs[0][1], runs[1][1])
+    fx = S.h.field(M.F64, 1, 0)
+    st = S.h.cg_solve(fx, b, tol=1e-10, timing=1)
+    assert st["t_precond"] == 0.0 and st["t_outer_op"] > 0 and st["t_blas"] > 0
