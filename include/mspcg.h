@@ -231,6 +231,24 @@ mspcg_status mspcg_debug_block_hop(mspcg_handle *h, const mspcg_precond *pc, int
 /* Conversions between storage precisions of one parity (same layout). */
 mspcg_status mspcg_convert(mspcg_handle *h, mspcg_field *out, const mspcg_field *in, void *stream);
 
+/* Allocation-free variant of mdagm, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops).  Same operator,
+ * kernels and layouts as mdagm; the two intermediate fields it needs live in
+ * a fixed scratch array of MSPCG_NOALLOC_SCRATCH_BYTES per GPU, held from the
+ * first handle created on that GPU until the process ends, instead of
+ * handle-owned memory.  Requirements, checked before any device work:
+ *   2 * nrhs * (V/2) * Ls * 24 * sizeof(storage real) <= MSPCG_NOALLOC_SCRATCH_BYTES
+ *   (plus the F16/BF16 norms, 2 * nrhs * (V/2) * Ls * 4 bytes), else MSPCG_EUNSUPPORTED;
+ *   links in the field's precision already prepared by the handle: always for F64 (done by
+ *   mspcg_create), for F32/F16/BF16 after any earlier operator call in that precision, else
+ *   MSPCG_EUNSUPPORTED.
+ * No hipMalloc, hipFree, event creation or launch-shape timing happens in this call: it uses
+ * the launch shapes already tuned for this operator on the handle, or the defaults.  Every
+ * call on one GPU shares that GPU's scratch array: calls that overlap in time on one GPU (other
+ * streams, other threads, other handles) race and give wrong results; serialise them. */
+#define MSPCG_NOALLOC_SCRATCH_BYTES (64u << 20)
+mspcg_status mdagm_noalloc(mspcg_handle *h, mspcg_field *out, const mspcg_field *in, void *stream);
+
 /* Description of the last error on this thread (empty if none). */
 const char *mspcg_last_error(void);
 

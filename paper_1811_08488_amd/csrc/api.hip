@@ -10,10 +10,18 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "internal.h"
+
+// Scratch of the allocation-free entry point mdagm_noalloc: its two
+// intermediate fields (each 256-byte aligned).  One copy per GPU, alive from
+// the library's first use on that GPU until the process ends.  Host code
+// never names it directly: the device address comes from hipGetSymbolAddress
+// (scratch_address below), resolved once per device.
+static __device__ __align__(256) unsigned char scratch[MSPCG_NOALLOC_SCRATCH_BYTES];
 
 namespace mspcg {
 // Precision-based inner stopping (inner_stop.hip): mode 0 after the initial
@@ -141,8 +149,31 @@ struct Mat5 {
 
 }  // namespace
 
+namespace {
+// Device address of `scratch` on the current device, looked up once per device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+
+void *scratch_address() {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(MSPCG_EUNSUPPORTED, "device ordinal above the scratch table size");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void *ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) fail(MSPCG_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_addr[dev] = ptr;
+  }
+  return g_scratch_addr[dev];
+}
+}  // namespace
+
 struct mspcg_handle {
   mspcg_dwf par;
+  int device = -1;                    // the HIP device the handle was created on
+  void *scratch_dev = nullptr;        // that device's copy of `scratch` (mdagm_noalloc)
   int V = 0, Vh = 0, Lxyz = 0;
   hipStream_t stream = nullptr;       // caller's stream given at creation (set-up work)
   hipStream_t work = nullptr;         // the solvers' own stream (default priority, capturable)
@@ -1114,6 +1145,8 @@ mspcg_status mspcg_create(mspcg_handle **hp, const mspcg_dwf *p, const double *g
     h->Vh = (int)(V / 2);
     h->Lxyz = p->L[0] * p->L[1] * p->L[2];
     h->stream = S(stream);
+    HIPCHK(hipGetDevice(&h->device));
+    h->scratch_dev = scratch_address();
     HIPCHK(hipStreamCreateWithFlags(&h->work, hipStreamNonBlocking));
     if (const char *e = std::getenv("MSPCG_AUTOTUNE")) h->autotune = std::atoi(e) != 0;
     if (const char *e = std::getenv("MSPCG_VERBOSE")) h->verbose = std::max(0, std::atoi(e));
@@ -1261,6 +1294,42 @@ mspcg_status mdagm(mspcg_handle *h, mspcg_field *out, const mspcg_field *in, voi
     h->tmp_o2.ensure(prec, nrhs, h->Vh, h->par.Ls);
     h->tmp_e2.ensure(prec, nrhs, h->Vh, h->par.Ls);
     apply_mdagm(h, prec, nrhs, vec_of(h, out), vec_of(h, in), h->tmp_o2.v, h->tmp_e2.v, nullptr, S(stream));
+  });
+}
+
+mspcg_status mdagm_noalloc(mspcg_handle *h, mspcg_field *out, const mspcg_field *in, void *stream) {
+  return guarded([&] {
+    if (!h) fail(MSPCG_EINVAL, "NULL handle");
+    check_field(h, out, "out");
+    check_field(h, in, "in");
+    if (out->parity != 0 || in->parity != 0) fail(MSPCG_EINVAL, "mdagm_noalloc acts on even fields");
+    if (out->prec != in->prec || out->nrhs != in->nrhs) fail(MSPCG_EINVAL, "mdagm_noalloc: precision/nrhs mismatch");
+    if (out->data == in->data) fail(MSPCG_EINVAL, "mdagm_noalloc: out must not alias in");
+    const int prec = in->prec, nrhs = in->nrhs, Ls = h->par.Ls;
+    if (!h->links_ok[prec])
+      fail(MSPCG_EUNSUPPORTED, "mdagm_noalloc: links of this precision not prepared (call an operator in it first)");
+    // two intermediate fields (odd, even), each with its norms, 256-byte aligned
+    auto align = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t n5 = (size_t)nrhs * h->Vh * Ls;
+    const size_t data_b = align(n5 * 24 * prec_bytes(prec));
+    const size_t norm_b = prec_norm(prec) ? align(n5 * sizeof(float)) : 0;
+    const size_t need = 2 * (data_b + norm_b);
+    if (need > (size_t)MSPCG_NOALLOC_SCRATCH_BYTES)
+      fail(MSPCG_EUNSUPPORTED, "mdagm_noalloc: the two intermediate fields need " + std::to_string(need) +
+                                   " bytes, above MSPCG_NOALLOC_SCRATCH_BYTES = " +
+                                   std::to_string((size_t)MSPCG_NOALLOC_SCRATCH_BYTES));
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != h->device) fail(MSPCG_EINVAL, "mdagm_noalloc: the current device is not the handle's device");
+    unsigned char *base = static_cast<unsigned char *>(h->scratch_dev);
+    Vec to, te;
+    to.prec = te.prec = prec;
+    to.stride = te.stride = h->Vh;
+    to.data = base;
+    to.norm = norm_b ? reinterpret_cast<float *>(base + data_b) : nullptr;
+    te.data = base + data_b + norm_b;
+    te.norm = norm_b ? reinterpret_cast<float *>(base + 2 * data_b + norm_b) : nullptr;
+    apply_mdagm(h, prec, nrhs, vec_of(h, out), vec_of(h, in), to, te, nullptr, S(stream), /*may_tune=*/false);
   });
 }
 

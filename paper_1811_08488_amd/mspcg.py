@@ -23,8 +23,10 @@ MAX_LS, MAX_NRHS = 32, 16
 EXPORTED = [
     "mspcg_create", "mspcg_destroy", "dslash_eo", "m5inv", "mdagm", "local_block_cg", "cg_solve", "mspcg_solve",
     "dwf_prepare_rhs", "dwf_reconstruct", "mspcg_debug_site_maps", "mspcg_debug_block_sites", "mspcg_convert",
-    "mspcg_block_apply", "mspcg_debug_block_hop", "mspcg_last_error",
+    "mspcg_block_apply", "mspcg_debug_block_hop", "mdagm_noalloc", "mspcg_last_error",
 ]
+# MSPCG_NOALLOC_SCRATCH_BYTES: scratch of mdagm_noalloc per GPU
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class Dwf(ctypes.Structure):
@@ -81,6 +83,7 @@ def lib():
             "mspcg_convert": [P, FP, FP, P],
             "mspcg_block_apply": [P, FP, FP, ctypes.POINTER(Precond), P],
             "mspcg_debug_block_hop": [P, ctypes.POINTER(Precond), I, I, I, P, P],
+            "mdagm_noalloc": [P, FP, FP, P],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -253,6 +256,9 @@ class Handle:
 
     def mdagm(self, out: Field, inp: Field, stream=None):
         _check(lib().mdagm(self.h, ctypes.byref(out.c()), ctypes.byref(inp.c()), _stream(stream)))
+
+    def mdagm_noalloc(self, out: Field, inp: Field, stream=None):
+        _check(lib().mdagm_noalloc(self.h, ctypes.byref(out.c()), ctypes.byref(inp.c()), _stream(stream)))
 
     def block_apply(self, out: Field, inp: Field, nblk, prec=F64, stream=None, no_snake=0):
         pc = Precond((ctypes.c_int * 4)(*nblk), 0, int(prec), int(no_snake), 0.0, 1)
