@@ -178,6 +178,7 @@ def time_block_hops(h, w, prec, nblk, reps=20, warm=3):
     import torch
 
     n_be = h.block_hop(nblk, prec, w.nrhs, 1, 0)[0]  # hop 1 reads the blocks' own even sites
+    torch.cuda.synchronize()  # (nothing else may run beside the timed launches)
     stream = torch.cuda.Stream()
     out = {}
     for hop in (1, 2, 3, 4):

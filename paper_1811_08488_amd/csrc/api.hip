@@ -124,7 +124,7 @@ struct BlockGeom {
   // or cleared for another layout, so that graphs captured on them are never replayed
   int vprec = -1, vnrhs = 0;
   long long gen = 0;
-  OwnedVec x, r, p, Ap, o1v, e2v;
+  OwnedVec x, r, p, mp, Ap, o1v, e2v;  // mp = M_phi p, the first hop's input
   DBuf stopbuf;  // precision-based inner stopping: [nb * nrhs][2] (inner_stop.hip)
   DBuf partial, scal, rrbuf;
 };
@@ -609,20 +609,33 @@ BlockGeom *get_blocks(mspcg_handle *h, const int nblk[4], int no_snake, hipStrea
   bg->be_tot = bg->be_off.back();
   bg->o1_tot = bg->o1_off.back();
   bg->e2_tot = bg->e2_off.back();
-  // a neighbour outside the domain (and every entry of a padding site) reads
-  // the target list's zero site, the first of its kPad extra sites
-  auto to_zero = [](std::vector<int> &t, int zero) {
-    for (int &x : t) {
-      if (x < 0) x = zero;
-      if (x > zero) fail(MSPCG_EINVAL, "internal: block table out of range");
+  // Neighbour tables: a neighbour outside the domain (a third of the first
+  // hop's, for example) is stored as -1 - alt, alt being an inside neighbour of
+  // the same site (or, for a padding site, one of the target list's kPad
+  // all-zero extra sites): the kernel loads alt's data, already at hand for
+  // another direction, and gives it weight zero, so these reads neither leave
+  // the cache nor converge on one all-zero site.
+  auto encode_out = [](std::vector<int> &t, int zero) {
+    for (size_t row = 0; row * 8 < t.size(); ++row) {
+      int alt = -1;
+      for (int d = 0; d < 8 && alt < 0; ++d) alt = t[row * 8 + d];
+      if (alt < 0) alt = zero + (int)(row % kPad);
+      for (int d = 0; d < 8; ++d) {
+        int &x = t[row * 8 + d];
+        if (x >= zero) fail(MSPCG_EINVAL, "internal: block table out of range");
+        if (x < 0) x = -1 - alt;
+      }
     }
   };
-  to_zero(be_nbr, bg->o1_tot);
-  to_zero(e2_nbr, bg->o1_tot);
-  to_zero(o1_nbr_e2, bg->e2_tot);
-  to_zero(o1_nbr_be, bg->be_tot);
-  to_zero(e2_be, bg->be_tot);
-  to_zero(be_e2, bg->e2_tot);
+  encode_out(be_nbr, bg->o1_tot);
+  encode_out(e2_nbr, bg->o1_tot);
+  encode_out(o1_nbr_e2, bg->e2_tot);
+  encode_out(o1_nbr_be, bg->be_tot);
+  // `other` index tables: -1 for a site whose operand lies outside (zero, not loaded)
+  for (int x : e2_be)
+    if (x >= bg->be_tot) fail(MSPCG_EINVAL, "internal: block table out of range");
+  for (int x : be_e2)
+    if (x >= bg->e2_tot) fail(MSPCG_EINVAL, "internal: block table out of range");
   upload(bg->d_be_cb, be_cb, st);
   upload(bg->d_be_blk, be_blk, st);
   upload(bg->d_be_nbr, be_nbr, st);
@@ -658,13 +671,14 @@ void ensure_block_vecs(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs) {
   const int Ls = h->par.Ls;
   const bool relayout = bg->vprec != prec || bg->vnrhs != nrhs;
   const std::vector<void *> before = {bg->x.data.p, bg->x.norm.p, bg->r.data.p, bg->r.norm.p, bg->p.data.p,
-                                      bg->p.norm.p, bg->Ap.data.p, bg->Ap.norm.p, bg->o1v.data.p, bg->o1v.norm.p,
+                                      bg->p.norm.p, bg->mp.data.p, bg->mp.norm.p, bg->Ap.data.p, bg->Ap.norm.p, bg->o1v.data.p, bg->o1v.norm.p,
                                       bg->e2v.data.p, bg->e2v.norm.p, bg->partial.p, bg->scal.p, bg->rrbuf.p,
                                       bg->stopbuf.p};
   // each list carries kPad extra sites after its last block: never written, so zero
   bg->x.ensure(prec, nrhs, bg->be_tot + kPad, Ls);
   bg->r.ensure(prec, nrhs, bg->be_tot + kPad, Ls);
   bg->p.ensure(prec, nrhs, bg->be_tot + kPad, Ls);
+  bg->mp.ensure(prec, nrhs, bg->be_tot + kPad, Ls);
   bg->Ap.ensure(prec, nrhs, bg->be_tot + kPad, Ls);
   bg->o1v.ensure(prec, nrhs, bg->o1_tot + kPad, Ls);
   bg->e2v.ensure(prec, nrhs, bg->e2_tot + kPad, Ls);
@@ -676,14 +690,14 @@ void ensure_block_vecs(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs) {
   if (relayout) {
     // the zero sites sit at other byte offsets in another precision or nrhs:
     // clear the buffers once so that they hold zeros again
-    for (OwnedVec *v : {&bg->x, &bg->r, &bg->p, &bg->Ap, &bg->o1v, &bg->e2v}) {
+    for (OwnedVec *v : {&bg->x, &bg->r, &bg->p, &bg->mp, &bg->Ap, &bg->o1v, &bg->e2v}) {
       if (v->data.p) HIPCHK(hipMemset(v->data.p, 0, v->data.bytes));
       if (v->norm.p) HIPCHK(hipMemset(v->norm.p, 0, v->norm.bytes));
     }
     HIPCHK(hipDeviceSynchronize());  // as in DBuf::ensure: the null stream orders nothing else
   }
   const std::vector<void *> after = {bg->x.data.p, bg->x.norm.p, bg->r.data.p, bg->r.norm.p, bg->p.data.p,
-                                     bg->p.norm.p, bg->Ap.data.p, bg->Ap.norm.p, bg->o1v.data.p, bg->o1v.norm.p,
+                                     bg->p.norm.p, bg->mp.data.p, bg->mp.norm.p, bg->Ap.data.p, bg->Ap.norm.p, bg->o1v.data.p, bg->o1v.norm.p,
                                      bg->e2v.data.p, bg->e2v.norm.p, bg->partial.p, bg->scal.p, bg->rrbuf.p,
                                      bg->stopbuf.p};
   if (relayout || before != after) {
@@ -714,15 +728,16 @@ HopArgs block_hop_args(mspcg_handle *h, int nrhs, int nsites, const int *site_cb
 
 // One of the four hops of A_s on the halo-extended domains, for every block at
 // once: 1: B_e -> O1, 2: O1 -> E2, 3: E2 -> O1, 4: O1 -> B_e (optional partial
-// Re<in, out> per workgroup).  Returns the grid size of the launch.
-int block_hop(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int which, const Vec &in, const Vec &out,
-              double *partial, hipStream_t st) {
+// Re<in, out> per workgroup).  in_mp = M_phi in (formed by the kernels that
+// write the block vector).  Returns the grid size of the launch.
+int block_hop(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int which, const Vec &in, const Vec &in_mp,
+              const Vec &out, double *partial, hipStream_t st) {
   if (which == 1) {  // c = M_phi M_5^{-1} (-1/2 H M_phi in) on O1
-    HopArgs a1 = block_hop_args(h, nrhs, bg->o1_tot, bg->d_o1_cb.as<int>(), bg->d_o1_nbr_be.as<int>(), in,
+    HopArgs a1 = block_hop_args(h, nrhs, bg->o1_tot, bg->d_o1_cb.as<int>(), bg->d_o1_nbr_be.as<int>(), in_mp,
                                 bg->o1v.v, 1, prec);
     a1.scale = -0.5;
     a1.mat = h->x1.ptr(prec);
-    return run_hop(h, 1, prec, 0, 1, EPI_DENSE, 0, 0, a1, st);
+    return run_hop(h, 1, prec, 0, 0, EPI_DENSE, 0, 0, a1, st);
   }
   if (which == 2) {  // y = M_5 in + 1/2 H c on E2
     HopArgs a2 = block_hop_args(h, nrhs, bg->e2_tot, bg->d_e2_cb.as<int>(), bg->d_e2_nbr.as<int>(), bg->o1v.v,
@@ -762,10 +777,10 @@ int block_hop(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int which, con
 
 // out = A_s in for every block at once on the halo-extended domains
 // (B_e -> O1 -> E2 -> O1 -> B_e); optional partial Re<in, out> per workgroup.
-int block_hops(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, const Vec &in, const Vec &out, double *partial,
-               hipStream_t st) {
-  for (int which = 1; which <= 3; ++which) block_hop(h, bg, prec, nrhs, which, in, out, nullptr, st);
-  const int grid = block_hop(h, bg, prec, nrhs, 4, in, out, partial, st);
+int block_hops(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, const Vec &in, const Vec &in_mp, const Vec &out,
+               double *partial, hipStream_t st) {
+  for (int which = 1; which <= 3; ++which) block_hop(h, bg, prec, nrhs, which, in, in_mp, out, nullptr, st);
+  const int grid = block_hop(h, bg, prec, nrhs, 4, in, in_mp, out, partial, st);
   return (bg->be_tot + grid - 1) / grid;  // sites per workgroup of the last hop
 }
 
@@ -779,6 +794,9 @@ BlockArgs block_args(mspcg_handle *h, BlockGeom *bg, int nrhs) {
   ba.be_blk = bg->d_be_blk.as<int>();
   ba.nblocks = bg->nb;
   ba.be_off = bg->d_be_off.as<int>();
+  ba.mphi_b = h->par.b;
+  ba.mphi_c = h->par.c;
+  ba.mf = h->par.mf;
   return ba;
 }
 
@@ -797,12 +815,12 @@ void run_block_cg(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int k, dou
   // inner_tol > 0: precision-based stopping (inner_stop.hip), else exactly k iterations
   const bool stop = inner_tol > 0.0;
   double *stopd = stop ? bg->stopbuf.as<double>() : nullptr;
-  HIPCHK(block_gather(prec, ba, bg->x.v, bg->r.v, bg->p.v, r, rr, n_total, part, st));
+  HIPCHK(block_gather(prec, ba, bg->x.v, bg->r.v, bg->p.v, bg->mp.v, r, rr, n_total, part, st));
   HIPCHK(block_scalars(2, ba, part, scal, st));
   if (stop) HIPCHK(inner_stop(0, bg->nb, nrhs, inner_tol, scal, stopd, st));
   for (int it = 0; it < k; ++it) {
     BlockArgs ba4 = ba;
-    ba4.nsite_wg = block_hops(h, bg, prec, nrhs, bg->p.v, bg->Ap.v, part, st);
+    ba4.nsite_wg = block_hops(h, bg, prec, nrhs, bg->p.v, bg->mp.v, bg->Ap.v, part, st);
     HIPCHK(block_scalars(0, ba4, part, scal, st));
     if (stop) HIPCHK(inner_stop(1, bg->nb, nrhs, inner_tol, scal, stopd, st));
     if (it + 1 < k) {
@@ -810,7 +828,7 @@ void run_block_cg(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int k, dou
       HIPCHK(block_update_r(prec, ba, bg->r.v, bg->Ap.v, scal, part, st));
       HIPCHK(block_scalars(1, ba, part, scal, st));
       if (stop) HIPCHK(inner_stop(2, bg->nb, nrhs, inner_tol, scal, stopd, st));
-      HIPCHK(block_update_xp(prec, ba, bg->x.v, bg->p.v, bg->r.v, scal, st));
+      HIPCHK(block_update_xp(prec, ba, bg->x.v, bg->p.v, bg->mp.v, bg->r.v, scal, st));
     } else {
       HIPCHK(block_update_xr(prec, ba, bg->x.v, bg->r.v, bg->p.v, bg->Ap.v, scal, part, st));
     }
@@ -1514,8 +1532,8 @@ mspcg_status mspcg_block_apply(mspcg_handle *h, mspcg_field *out, const mspcg_fi
     BlockArgs ba = block_args(h, bg, nrhs);
     const double n_total = (double)h->Vh * h->par.Ls * 24;
     double *part = bg->partial.as<double>();
-    HIPCHK(block_gather(prec, ba, bg->x.v, bg->r.v, bg->p.v, vec_of(h, in), nullptr, n_total, part, st));
-    (void)block_hops(h, bg, prec, nrhs, bg->p.v, bg->Ap.v, nullptr, st);
+    HIPCHK(block_gather(prec, ba, bg->x.v, bg->r.v, bg->p.v, bg->mp.v, vec_of(h, in), nullptr, n_total, part, st));
+    (void)block_hops(h, bg, prec, nrhs, bg->p.v, bg->mp.v, bg->Ap.v, nullptr, st);
     HIPCHK(block_scatter(prec, ba, vec_of(h, out), bg->Ap.v, Vec(), nullptr, n_total, part, st));
   });
 }
@@ -1534,7 +1552,8 @@ mspcg_status mspcg_debug_block_hop(mspcg_handle *h, const mspcg_precond *pc, int
     ensure_links(h, prec, st);
     ensure_block_vecs(h, bg, prec, nrhs);
     double *part = bg->partial.as<double>();
-    for (int i = 0; i < reps; ++i) block_hop(h, bg, prec, nrhs, hop, bg->p.v, bg->Ap.v, hop == 4 ? part : nullptr, st);
+    for (int i = 0; i < reps; ++i)
+      block_hop(h, bg, prec, nrhs, hop, bg->p.v, bg->mp.v, bg->Ap.v, hop == 4 ? part : nullptr, st);
     if (sites) {
       // input and output domains: 1: B_e -> O1, 2: O1 -> E2, 3: E2 -> O1, 4: O1 -> B_e
       long long nbe = 0, no1 = 0, ne2 = 0;

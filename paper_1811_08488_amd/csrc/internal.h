@@ -31,7 +31,8 @@ struct HopArgs {
   int Ls, nrhs, nsite_wg;
   const int *site_cb;  // [nsites] cb of the output site in the full lattice (-1: padding)
   const int *nbr;      // [site][8] input index of neighbour d = 2 mu + (0 fwd, 1 bwd); indexed by cb for the
-                       // full lattice, by list position for block domains (outside: the input's zero site)
+                       // full lattice, by list position for block domains, where a neighbour outside the
+                       // domain is stored as -1 - alt (alt: an input index whose data is loaded with weight 0)
   int zero_site;       // input index read by inactive threads (an all-zero site of block lists)
   const void *in;
   const float *in_norm;
@@ -43,7 +44,7 @@ struct HopArgs {
   const void *other;   // EPI_M5_OTHER / EPI_M5DAG_MPHIDAG operand
   const float *other_norm;
   long long other_stride;
-  const int *other_idx;  // output list position -> index in `other`; nullptr: identity
+  const int *other_idx;  // output list position -> index in `other`, -1 outside (zero); nullptr: identity
   int other_zero;        // zero site of `other` (inactive threads)
   double scale;
   const void *mat;     // EPI_DENSE: [2][Ls][Ls] row-major (chirality +, then -) in the compute type
@@ -112,10 +113,12 @@ struct BlockArgs {
   const int *be_blk;  // [nsites] block of the site (-1: padding)
   int nblocks;
   const int *be_off;  // [nblocks+1] padded offsets (multiples of the block alignment, itself a multiple of 64)
+  double mphi_b, mphi_c, mf;  // M_phi = b + c P_chi (the first block hop reads M_phi p, formed where p is)
 };
-// r_s = p_s = scale * r(cb), x_s = 0; partial |r_s|^2 per workgroup.  scale = sqrt(n_total/rr[rhs]).
-hipError_t block_gather(int prec, const BlockArgs &b, const Vec &xs, const Vec &rs, const Vec &ps, const Vec &rglob,
-                        const double *rr, double n_total, double *partial, hipStream_t st);
+// r_s = p_s = scale * r(cb), mp_s = M_phi p_s, x_s = 0; partial |r_s|^2 per workgroup.
+// scale = sqrt(n_total/rr[rhs]).
+hipError_t block_gather(int prec, const BlockArgs &b, const Vec &xs, const Vec &rs, const Vec &ps, const Vec &mps,
+                        const Vec &rglob, const double *rr, double n_total, double *partial, hipStream_t st);
 // z(cb) = x_s / scale; partial Re<z, r> per workgroup (FP64 r, z)
 hipError_t block_scatter(int prec, const BlockArgs &b, const Vec &zglob, const Vec &xs, const Vec &rglob,
                          const double *rr, double n_total, double *partial, hipStream_t st);
@@ -129,9 +132,9 @@ hipError_t block_update_xr(int prec, const BlockArgs &b, const Vec &x, const Vec
 // r -= alpha Ap, partial |r|^2 (the other inner iterations) ...
 hipError_t block_update_r(int prec, const BlockArgs &b, const Vec &r, const Vec &Ap, const double *scal,
                           double *partial, hipStream_t st);
-// ... then, once beta is known, x += alpha p and p = r + beta p
-hipError_t block_update_xp(int prec, const BlockArgs &b, const Vec &x, const Vec &p, const Vec &r, const double *scal,
-                           hipStream_t st);
+// ... then, once beta is known, x += alpha p, p = r + beta p and mp = M_phi p
+hipError_t block_update_xp(int prec, const BlockArgs &b, const Vec &x, const Vec &p, const Vec &mp, const Vec &r,
+                           const double *scal, hipStream_t st);
 
 // scal layout per (block, rhs): [rho, alpha, beta, pad]
 constexpr int kScal = 4;

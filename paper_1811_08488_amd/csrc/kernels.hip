@@ -175,15 +175,16 @@ __device__ inline void project_pre(R *lds, int nthr, int tid, int s, int Ls, R c
   for (int k = 0; k < 12; ++k) h[k] = fma(cl, Yw[k], fma(cu, Xw[k], X[k] + Y[k]));
 }
 
+// wt: the neighbour's weight (1, or 0 outside a block domain; only without M_phi on the input)
 template <int MU, int SGN, int PRE, int XM, typename R>
 __device__ inline void hop_dir(R *lds, int nthr, int tid, int s, int Ls, R cu, R cl, const R v[24], const R *U,
-                               R acc[24]) {
+                               R acc[24], R wt) {
   R h[12];
   if (PRE)
     project_pre<MU, SGN, XM>(lds, nthr, tid, s, Ls, cu, cl, v, h);
   else
     project<MU, SGN>(v, h);
-  hop_half<MU, SGN>(h, U, acc, R(1));
+  hop_half<MU, SGN>(h, U, acc, wt);
 }
 
 __device__ inline uint32_t rot_prev_word(uint32_t x) { return (uint32_t)rot_prev_dpp((int)x); }
@@ -241,7 +242,7 @@ __device__ inline void exchange_pre_raw(float *lds, int nthr, int tid, int s, in
 // each sum a multiply-add.
 template <int MU, int SGN, int PRE, int XM, typename S>
 __device__ inline void hop_dir_norm(float *lds, int nthr, int tid, int s, int Ls, float cu, float cl, float one,
-                                    const RawSite<S> &raw, const float *U, float acc[24]) {
+                                    const RawSite<S> &raw, const float *U, float acc[24], bool out) {
   // every direction widens its own copy of the stored words: shared by the
   // eight direction variants, the widening would be hoisted out of them as
   // separate conversions instead of folding into the multiply-adds
@@ -255,7 +256,7 @@ __device__ inline void hop_dir_norm(float *lds, int nthr, int tid, int s, int Ls
   float v[24], X[12], Y[12], h[12];
   rs.decode_raw(v);
   project_parts<MU, SGN>(v, X, Y);
-  float n = raw.n;
+  float n = out ? 0.f : raw.n;
   if (PRE) {
     RawSite<S> w;
     float nm, np;
@@ -283,13 +284,13 @@ __device__ inline void hop_dir_norm(float *lds, int nthr, int tid, int s, int Ls
 // half-precision sum cannot overflow; m multiplies the link product.
 template <int MU, int SGN, int PRE, int XM>
 __device__ inline void hop_dir_h16(float *lds, int nthr, int tid, int s, int Ls, float cu, float cl,
-                                   const RawSite<_Float16> &raw, const uint32_t *U, float acc[24]) {
+                                   const RawSite<_Float16> &raw, const uint32_t *U, float acc[24], bool out) {
   uint32_t wd[12];
 #pragma unroll
   for (int i = 0; i < 12; ++i) wd[i] = raw.word(i);
   half2_t X[6], Y[6], h[6];
   project_parts_h16<MU, SGN>(wd, X, Y);
-  float m = raw.n;
+  float m = out ? 0.f : raw.n;
   if (PRE) {
     RawSite<_Float16> w;
     float nm, np;
@@ -551,13 +552,24 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
   // The eight neighbour indices are loaded once, with two 16-byte loads, and
   // kept in registers (rotated by two per direction pair below): no spinor
   // load ever waits for an index load issued after an earlier spinor load.
+  // Block domains: bit d of outm marks a neighbour outside the domain, whose
+  // (substitute) data enters with weight zero.
   int nbw[8];
+  int outm = 0;
   {
     const int4 *nb4 = reinterpret_cast<const int4 *>(a.nbr + (size_t)(active ? self : 0) * 8);
     const int4 q0 = nb4[0], q1 = nb4[1];
     const int qa[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
 #pragma unroll
-    for (int d = 0; d < 8; ++d) nbw[d] = active ? qa[d] : a.zero_site;
+    for (int d = 0; d < 8; ++d) {
+      if (GLOBAL) {
+        nbw[d] = active ? qa[d] : a.zero_site;
+      } else {  // (inactive lanes read zero sites, spread over the kPad of them)
+        const bool out = qa[d] < 0;
+        nbw[d] = active ? (out ? -1 - qa[d] : qa[d]) : a.zero_site + ((site * 8 + d) & 63);
+        outm |= (active && out) ? (1 << d) : 0;
+      }
+    }
   }
   // the first neighbour spinor is requested before anything else waits
   const S *in = reinterpret_cast<const S *>(a.in);
@@ -622,21 +634,23 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
       // (1 - g_mu) for the forward hop of H and the backward hop of H^+
       constexpr int sp = (DAG != 0) ? -1 : 1;
       const int sg = bw ? -sp : sp;
+      const bool out = !GLOBAL && ((outm >> d) & 1);
 #define MSPCG_DIR(M)                                                                                        \
   if constexpr (kH16) {                                                                                     \
     const RawSite<S> &raw = (bw == 0 || !kPrefetch) ? cur : nxt;                                           \
     const uint32_t *Uw = reinterpret_cast<const uint32_t *>(U);                                            \
-    if (sg > 0) hop_dir_h16<M, 1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, raw, Uw, acc);                  \
-    else hop_dir_h16<M, -1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, raw, Uw, acc);                        \
+    if (sg > 0) hop_dir_h16<M, 1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, raw, Uw, acc, out);             \
+    else hop_dir_h16<M, -1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, raw, Uw, acc, out);                   \
   } else if constexpr (Traits<S>::kNorm) {                                                                  \
     const RawSite<S> &raw = (bw == 0 || !kPrefetch) ? cur : nxt;                                           \
-    if (sg > 0) hop_dir_norm<M, 1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, one, raw, U, acc);             \
-    else hop_dir_norm<M, -1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, one, raw, U, acc);                   \
+    if (sg > 0) hop_dir_norm<M, 1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, one, raw, U, acc, out);        \
+    else hop_dir_norm<M, -1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, one, raw, U, acc, out);              \
   } else {                                                                                                  \
     R v[24];                                                                                                \
     if (bw == 0 || !kPrefetch) cur.decode(v); else nxt.decode(v);                                           \
-    if (sg > 0) hop_dir<M, 1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, v, U, acc);                         \
-    else hop_dir<M, -1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, v, U, acc);                               \
+    const R wt = out ? R(0) : R(1);                                                                         \
+    if (sg > 0) hop_dir<M, 1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, v, U, acc, wt);                     \
+    else hop_dir<M, -1, PRE, XM>(lds, nthr, tid, s, Ls, pcu, pcl, v, U, acc, wt);                           \
   }
       switch (mu) {
         case 0: MSPCG_DIR(0) break;
@@ -665,9 +679,11 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
     for (int k = 0; k < 24; ++k) acc[k] *= scale;
   }
   if (EPI == EPI_M5_OTHER || EPI == EPI_M5DAG_MPHIDAG) {
-    const int oi = GLOBAL ? cb : (active ? (a.other_idx ? a.other_idx[site] : site) : a.other_zero);
+    int oi = GLOBAL ? cb : (active ? (a.other_idx ? a.other_idx[site] : site) : -1);
     R o[24];
-    load24<R>(reinterpret_cast<const S *>(a.other), a.other_norm, (size_t)r * a.other_stride + oi, s, Ls, o);
+    zero24(o);
+    if (oi >= 0)  // (outside the block domain the operand vanishes)
+      load24<R>(reinterpret_cast<const S *>(a.other), a.other_norm, (size_t)r * a.other_stride + oi, s, Ls, o);
     // M_5 = alpha - beta P_chi ; M_5^+ = alpha - beta P_chi^+
     pchi_comb<EPI == EPI_M5DAG_MPHIDAG ? 1 : 0, XM, R>(lds, nthr, tid, s, Ls, (R)a.m5_alpha, (R)(-a.m5_beta), (R)a.mf,
                                                      o);
@@ -733,7 +749,9 @@ static hipError_t dispatch_hop(int dagger, int pre, int epi, int dot, int global
   MSPCG_HOP(1, 0, EPI_DENSE, 0, 1)          // M_5^-+ (M^4)^+ y
   MSPCG_HOP(1, 0, EPI_M5DAG_MPHIDAG, 0, 1)  // M_5^+ y + 1/2 M_phi^+ H^+ f
   MSPCG_HOP(1, 0, EPI_M5DAG_MPHIDAG, 1, 1)  //   ... with the fused <w, out>
-  MSPCG_HOP(0, 1, EPI_DENSE, 0, 0)          // the same four hops on block domains
+  MSPCG_HOP(0, 0, EPI_DENSE, 0, 0)          // the same four hops on block domains (M_phi p formed beforehand;
+                                            // neighbours outside a domain enter with weight zero, which needs
+                                            // the input unmixed: no M_phi on the input there)
   MSPCG_HOP(0, 0, EPI_M5_OTHER, 0, 0)
   MSPCG_HOP(1, 0, EPI_DENSE, 0, 0)
   MSPCG_HOP(1, 0, EPI_M5DAG_MPHIDAG, 0, 0)
@@ -1013,28 +1031,37 @@ hipError_t solver_scalars(int mode, int nrhs, const int *active, double *rho, co
 // ---------------------------------------------------------------- block preconditioner
 // The B_e list is ordered block by block, each block padded to a multiple of
 // 64 sites, so with nsite_wg dividing 64 every workgroup lies in one block.
+// M_phi v = b v + c P_chi v for the Ls values of one (site, rhs) held on
+// consecutive threads of a block kernel (layout tid = s + Ls (rhs + nrhs site)),
+// exchanged through LDS; all threads of the workgroup must reach it.
+template <typename R>
+__device__ inline void block_mphi(R *lds, int nthr, int tid, int s, int Ls, const BlockArgs &b, R v[24]) {
+  pchi_comb<0, kXLds, R>(lds, nthr, tid, s, Ls, (R)b.mphi_b, (R)b.mphi_c, (R)b.mf, v);
+}
+
 template <typename S>
-__global__ void __launch_bounds__(256) k_block_gather(const BlockArgs b, Vec xs, Vec rs, Vec ps, const double *rg,
-                                                       long long rg_stride, const double *rr, double n_total,
-                                                       double *partial) {
+__global__ void __launch_bounds__(256) k_block_gather(const BlockArgs b, Vec xs, Vec rs, Vec ps, Vec mps,
+                                                       const double *rg, long long rg_stride, const double *rr,
+                                                       double n_total, double *partial) {
   using R = typename Traits<S>::R;
   extern __shared__ __align__(16) unsigned char smem[];
   const int nthr = blockDim.x, tid = threadIdx.x, Ls = b.Ls, G = b.nrhs * Ls;
   const int sl = tid / G, rem = tid - sl * G, r = rem / Ls, s = rem - r * Ls;
   const int site = blockIdx.x * b.nsite_wg + sl;
   const int cb = site < b.nsites ? b.be_cb[site] : -1;
+  const size_t o = (size_t)r * rs.stride + site;
   double val = 0;
+  R v[24];
+  zero24(v);
   if (cb >= 0) {
     const double scale = rr ? (rr[r] > 0 ? sqrt(n_total / rr[r]) : 0.0) : 1.0;
     double t[24];
     load24<double>(rg, nullptr, (size_t)r * rg_stride + cb, s, Ls, t);
-    R v[24];
 #pragma unroll
     for (int k = 0; k < 24; ++k) v[k] = (R)(scale * t[k]);
-    const size_t o = (size_t)r * rs.stride + site;
     store24<R>(reinterpret_cast<S *>(rs.data), rs.norm, o, s, Ls, v);
-    // read back what was stored so that r and p start identical and the sum matches them
-    load24<R>(reinterpret_cast<const S *>(rs.data), rs.norm, o, s, Ls, v);
+    // the values as stored, so that r and p start identical and the sum matches them
+    stored_values<S>(v);
     store24<R>(reinterpret_cast<S *>(ps.data), ps.norm, o, s, Ls, v);
     R z[24];
     zero24(z);
@@ -1044,6 +1071,8 @@ __global__ void __launch_bounds__(256) k_block_gather(const BlockArgs b, Vec xs,
     for (int k = 0; k < 24; ++k) acc += v[k] * v[k];
     val = (double)acc;
   }
+  block_mphi<R>(reinterpret_cast<R *>(smem), nthr, tid, s, Ls, b, v);
+  if (cb >= 0) store24<R>(reinterpret_cast<S *>(mps.data), mps.norm, o, s, Ls, v);
   wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, b.nrhs, b.nsite_wg, 0, val, partial, blockIdx.x);
 }
 
@@ -1142,30 +1171,38 @@ __global__ void __launch_bounds__(256) k_block_update_r(const BlockArgs b, Vec r
 }
 
 // x += alpha p, then p = r + beta p (the x update of k_block_update_xr moved
-// here, where p is read anyway)
+// here, where p is read anyway), and M_phi p for the next first hop (from the
+// values as stored)
 template <typename S>
-__global__ void __launch_bounds__(256) k_block_update_xp(const BlockArgs b, Vec xv, Vec pv, Vec rv,
+__global__ void __launch_bounds__(256) k_block_update_xp(const BlockArgs b, Vec xv, Vec pv, Vec mpv, Vec rv,
                                                          const double *scal) {
   using R = typename Traits<S>::R;
-  const int tid = threadIdx.x, Ls = b.Ls, G = b.nrhs * Ls;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nthr = blockDim.x, tid = threadIdx.x, Ls = b.Ls, G = b.nrhs * Ls;
   const int sl = tid / G, rem = tid - sl * G, r = rem / Ls, s = rem - r * Ls;
   const int site = blockIdx.x * b.nsite_wg + sl;
   const int blk = site < b.nsites ? b.be_blk[site] : -1;
-  if (blk < 0) return;
-  const double *sc = scal + ((size_t)blk * b.nrhs + r) * kScal;
-  const R al = (R)sc[1], be = (R)sc[2];
   const size_t o = (size_t)r * pv.stride + site;
-  R x[24], p[24], rr[24];
-  load24<R>(reinterpret_cast<const S *>(xv.data), xv.norm, o, s, Ls, x);
-  load24<R>(reinterpret_cast<const S *>(pv.data), pv.norm, o, s, Ls, p);
-  load24<R>(reinterpret_cast<const S *>(rv.data), rv.norm, o, s, Ls, rr);
+  R p[24];
+  zero24(p);
+  if (blk >= 0) {
+    const double *sc = scal + ((size_t)blk * b.nrhs + r) * kScal;
+    const R al = (R)sc[1], be = (R)sc[2];
+    R x[24], rr[24];
+    load24<R>(reinterpret_cast<const S *>(xv.data), xv.norm, o, s, Ls, x);
+    load24<R>(reinterpret_cast<const S *>(pv.data), pv.norm, o, s, Ls, p);
+    load24<R>(reinterpret_cast<const S *>(rv.data), rv.norm, o, s, Ls, rr);
 #pragma unroll
-  for (int k = 0; k < 24; ++k) {
-    x[k] += al * p[k];
-    p[k] = rr[k] + be * p[k];
+    for (int k = 0; k < 24; ++k) {
+      x[k] += al * p[k];
+      p[k] = rr[k] + be * p[k];
+    }
+    store24<R>(reinterpret_cast<S *>(xv.data), xv.norm, o, s, Ls, x);
+    store24<R>(reinterpret_cast<S *>(pv.data), pv.norm, o, s, Ls, p);
+    stored_values<S>(p);
   }
-  store24<R>(reinterpret_cast<S *>(xv.data), xv.norm, o, s, Ls, x);
-  store24<R>(reinterpret_cast<S *>(pv.data), pv.norm, o, s, Ls, p);
+  block_mphi<R>(reinterpret_cast<R *>(smem), nthr, tid, s, Ls, b, p);
+  if (blk >= 0) store24<R>(reinterpret_cast<S *>(mpv.data), mpv.norm, o, s, Ls, p);
 }
 
 // one workgroup per (block, rhs): a fixed-shape tree sum of that block's
@@ -1200,6 +1237,11 @@ __global__ void __launch_bounds__(256) k_block_scalars(int mode, int nrhs, int n
 static inline int block_threads(const BlockArgs &b) { return b.nsite_wg * b.nrhs * b.Ls; }
 static inline int block_grid(const BlockArgs &b) { return (b.nsites + b.nsite_wg - 1) / b.nsite_wg; }
 static inline size_t block_lds(const BlockArgs &b) { return (size_t)2 * block_threads(b) * sizeof(double); }
+// the kernels that form M_phi p exchange 24 reals per thread through LDS
+template <typename S>
+static inline size_t block_lds_mphi(const BlockArgs &b) {
+  return std::max(block_lds(b), (size_t)24 * block_threads(b) * sizeof(typename Traits<S>::R));
+}
 
 #define MSPCG_PREC_SWITCH(prec, CALL)                 \
   switch (prec) {                                     \
@@ -1210,12 +1252,12 @@ static inline size_t block_lds(const BlockArgs &b) { return (size_t)2 * block_th
     default: return hipErrorInvalidValue;             \
   }
 
-hipError_t block_gather(int prec, const BlockArgs &b, const Vec &xs, const Vec &rs, const Vec &ps, const Vec &rglob,
-                        const double *rr, double n_total, double *partial, hipStream_t st) {
+hipError_t block_gather(int prec, const BlockArgs &b, const Vec &xs, const Vec &rs, const Vec &ps, const Vec &mps,
+                        const Vec &rglob, const double *rr, double n_total, double *partial, hipStream_t st) {
   if (rglob.prec != MSPCG_F64 || block_threads(b) > 256) return hipErrorInvalidValue;
   MSPCG_PREC_SWITCH(prec, hipLaunchKernelGGL(k_block_gather<S>, dim3(block_grid(b)), dim3(block_threads(b)),
-                                             block_lds(b), st, b, xs, rs, ps, (const double *)rglob.data,
-                                             rglob.stride, rr, n_total, partial));
+                                             block_lds_mphi<S>(b), st, b, xs, rs, ps, mps,
+                                             (const double *)rglob.data, rglob.stride, rr, n_total, partial));
   return hipGetLastError();
 }
 
@@ -1252,11 +1294,11 @@ hipError_t block_update_r(int prec, const BlockArgs &b, const Vec &r, const Vec 
   return hipGetLastError();
 }
 
-hipError_t block_update_xp(int prec, const BlockArgs &b, const Vec &x, const Vec &p, const Vec &r, const double *scal,
-                           hipStream_t st) {
+hipError_t block_update_xp(int prec, const BlockArgs &b, const Vec &x, const Vec &p, const Vec &mp, const Vec &r,
+                           const double *scal, hipStream_t st) {
   if (block_threads(b) > 256) return hipErrorInvalidValue;
-  MSPCG_PREC_SWITCH(prec, hipLaunchKernelGGL(k_block_update_xp<S>, dim3(block_grid(b)), dim3(block_threads(b)), 0,
-                                             st, b, x, p, r, scal));
+  MSPCG_PREC_SWITCH(prec, hipLaunchKernelGGL(k_block_update_xp<S>, dim3(block_grid(b)), dim3(block_threads(b)),
+                                             block_lds_mphi<S>(b), st, b, x, p, mp, r, scal));
   return hipGetLastError();
 }
 
