@@ -140,8 +140,8 @@ int block_align(int Ls) {
   return (G > 0 && (G & (G - 1)) != 0) ? kPad * G : kPad;
 }
 
-// A dense fifth-dimension operator [2][Ls][Ls] in FP64 and FP32 (the compute
-// types of the kernels).
+// The chain coefficients of a fifth-dimension operator in FP64 and FP32 (the
+// compute types of the kernels).
 struct Mat5 {
   DBuf d, f;
   const void *ptr(int prec) const { return prec == MSPCG_F64 ? d.p : f.p; }
@@ -187,7 +187,7 @@ struct mspcg_handle {
   bool links_ok[4] = {false, false, false, false};
   DBuf d_gauge;
   // dense fifth-dimension matrices [2][Ls][Ls]
-  Mat5 m5inv, m5inv_t, x1, x3;
+  Mat5 m5inv, x1;  // chain coefficients of M_5^{-1} and of M_phi M_5^{-1} (the kernels also apply the transposes)
   // FP64 workspaces
   OwnedVec tmp_o, tmp_e, tmp_o2, tmp_e2, sr, sp, sq, sz;
   OwnedVec sw_t, sw_z, sw_q;  // multisplitting sweeps: r - A z, the sweep's correction, A z
@@ -234,59 +234,21 @@ int pick_nsite(int nrhs, int Ls) {
 }
 
 // ------------------------------------------------------------- fifth dimension
-// Per chirality the operators are Ls x Ls real matrices: on chirality +
-// P_chi acts as S-, on chirality - as S+ (S^Ls = -mf).
-typedef std::vector<double> Mat;  // row-major Ls x Ls
-
-Mat shift(int Ls, double mf, bool up) {
-  Mat S(Ls * Ls, 0.0);
-  for (int s = 0; s < Ls; ++s) {
-    if (up) {
-      if (s < Ls - 1) S[s * Ls + s + 1] = 1; else S[s * Ls + 0] = -mf;
-    } else {
-      if (s > 0) S[s * Ls + s - 1] = 1; else S[s * Ls + Ls - 1] = -mf;
-    }
-  }
-  return S;
-}
-Mat matmul(const Mat &A, const Mat &B, int n) {
-  Mat C(n * n, 0.0);
-  for (int i = 0; i < n; ++i)
-    for (int k = 0; k < n; ++k)
-      for (int j = 0; j < n; ++j) C[i * n + j] += A[i * n + k] * B[k * n + j];
-  return C;
-}
-Mat transpose(const Mat &A, int n) {
-  Mat T(n * n);
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) T[j * n + i] = A[i * n + j];
-  return T;
-}
-// (alpha - beta S)^{-1} = sum_k q^k S^k / (alpha (1 + mf q^Ls)),  q = beta / alpha
-Mat m5inv_chiral(int Ls, double alpha, double beta, double mf, bool up) {
-  Mat S = shift(Ls, mf, up), P(Ls * Ls, 0.0), acc(Ls * Ls, 0.0);
-  for (int i = 0; i < Ls; ++i) P[i * Ls + i] = 1;
+// Chain coefficients (see kChainHead) of X = (b_phi / alpha)(1 + rho S)(1 - q S)^{-1},
+// q = beta / alpha, per chirality: M_5^{-1} with rho = 0, b_phi = 1 and
+// M_phi M_5^{-1} = (b + c S)(alpha - beta S)^{-1} with rho = c / b, b_phi = b
+// (S^Ls = -mf, so (1 - q S)^{-1} = sum_k q^k S^k / (1 + mf q^Ls)).
+std::vector<double> chain_coefs(int Ls, double alpha, double beta, double mf, double rho, double b_phi) {
   const double q = beta / alpha;
-  double qk = 1;
-  for (int k = 0; k < Ls; ++k) {
-    for (int i = 0; i < Ls * Ls; ++i) acc[i] += qk * P[i];
-    P = matmul(P, S, Ls);
-    qk *= q;
-  }
-  const double den = alpha * (1 + mf * std::pow(q, Ls));
-  for (auto &x : acc) x /= den;
-  return acc;
-}
-Mat mphi_chiral(int Ls, double b, double c, double mf, bool up) {
-  Mat M = shift(Ls, mf, up);
-  for (auto &x : M) x *= c;
-  for (int i = 0; i < Ls; ++i) M[i * Ls + i] += b;
-  return M;
-}
-std::vector<double> pack2(const Mat &plus, const Mat &minus) {
-  std::vector<double> v(plus);
-  v.insert(v.end(), minus.begin(), minus.end());
-  return v;
+  const double gamma = -q * mf / (1.0 + mf * std::pow(q, Ls));
+  std::vector<double> c(kChainHead + Ls);
+  c[0] = rho;
+  c[1] = -rho * mf;
+  c[2] = q;
+  c[3] = b_phi / alpha;
+  double qi = 1.0;
+  for (int i = 0; i < Ls; ++i, qi *= q) c[kChainHead + i] = gamma * qi;
+  return c;
 }
 
 // ------------------------------------------------------------- validation
@@ -448,11 +410,11 @@ int global_hop(mspcg_handle *h, int prec, int nrhs, int p, const Vec &out, const
 int apply_mdagm(mspcg_handle *h, int prec, int nrhs, const Vec &out, const Vec &in, const Vec &to, const Vec &te,
                 double *partial, hipStream_t st, bool may_tune = true) {
   // c_o = M_phi M_5^{-1} (-1/2 H_oe M_phi in)
-  global_hop(h, prec, nrhs, 1, to, in, 0, 1, EPI_DENSE, -0.5, &h->x1, nullptr, nullptr, nullptr, st, may_tune);
+  global_hop(h, prec, nrhs, 1, to, in, 0, 1, EPI_M5INV, -0.5, &h->x1, nullptr, nullptr, nullptr, st, may_tune);
   // y_e = M_5 in + 1/2 H_eo c_o  (= D_PC in)
   global_hop(h, prec, nrhs, 0, te, to, 0, 0, EPI_M5_OTHER, 0.5, nullptr, &in, nullptr, nullptr, st, may_tune);
   // f_o = M_5^{-+} M_phi^+ (-1/2 H^+_oe y_e)
-  global_hop(h, prec, nrhs, 1, to, te, 1, 0, EPI_DENSE, -0.5, &h->x3, nullptr, nullptr, nullptr, st, may_tune);
+  global_hop(h, prec, nrhs, 1, to, te, 1, 0, EPI_M5INV, -0.5, &h->x1, nullptr, nullptr, nullptr, st, may_tune);
   // out = M_5^+ y + 1/2 M_phi^+ H^+_eo f  (= D_PC^+ y)
   return global_hop(h, prec, nrhs, 0, out, to, 1, 0, EPI_M5DAG_MPHIDAG, 0.5, nullptr, &te, partial, &in, st,
                     may_tune);
@@ -737,7 +699,7 @@ int block_hop(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int which, con
                                 bg->o1v.v, 1, prec);
     a1.scale = -0.5;
     a1.mat = h->x1.ptr(prec);
-    return run_hop(h, 1, prec, 0, 0, EPI_DENSE, 0, 0, a1, st);
+    return run_hop(h, 1, prec, 0, 0, EPI_M5INV, 0, 0, a1, st);
   }
   if (which == 2) {  // y = M_5 in + 1/2 H c on E2
     HopArgs a2 = block_hop_args(h, nrhs, bg->e2_tot, bg->d_e2_cb.as<int>(), bg->d_e2_nbr.as<int>(), bg->o1v.v,
@@ -754,8 +716,8 @@ int block_hop(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int which, con
     HopArgs a3 = block_hop_args(h, nrhs, bg->o1_tot, bg->d_o1_cb.as<int>(), bg->d_o1_nbr_e2.as<int>(), bg->e2v.v,
                                 bg->o1v.v, 1, prec);
     a3.scale = -0.5;
-    a3.mat = h->x3.ptr(prec);
-    return run_hop(h, 3, prec, 1, 0, EPI_DENSE, 0, 0, a3, st);
+    a3.mat = h->x1.ptr(prec);  // (the daggered hop applies the transpose)
+    return run_hop(h, 3, prec, 1, 0, EPI_M5INV, 0, 0, a3, st);
   }
   // out = M_5^+ y + 1/2 M_phi^+ H^+ f on B_e
   HopArgs a4 = block_hop_args(h, nrhs, bg->be_tot, bg->d_be_cb.as<int>(), bg->d_be_nbr.as<int>(), bg->o1v.v, out,
@@ -1231,20 +1193,13 @@ mspcg_status mspcg_create(mspcg_handle **hp, const mspcg_dwf *p, const double *g
     h->d_gauge.ensure((size_t)V * 4 * 18 * sizeof(double));
     HIPCHK(hipMemcpyAsync(h->d_gauge.p, gauge, (size_t)V * 4 * 18 * sizeof(double), hipMemcpyDeviceToDevice, st));
     ensure_links(h.get(), MSPCG_F64, st);
-    // fifth-dimension matrices per chirality (+: S-, -: S+)
-    Mat ip = m5inv_chiral(Ls, h->alpha5, h->beta5, p->mf, false);
-    Mat im = m5inv_chiral(Ls, h->alpha5, h->beta5, p->mf, true);
-    Mat pp = mphi_chiral(Ls, p->b, p->c, p->mf, false);
-    Mat pm = mphi_chiral(Ls, p->b, p->c, p->mf, true);
-    Mat x1p = matmul(pp, ip, Ls), x1m = matmul(pm, im, Ls);
+    // fifth-dimension operators as chain coefficients
     auto up5 = [&](Mat5 &m, const std::vector<double> &v) {
       upload(m.d, v, st);
       upload(m.f, std::vector<float>(v.begin(), v.end()), st);
     };
-    up5(h->m5inv, pack2(ip, im));
-    up5(h->m5inv_t, pack2(transpose(ip, Ls), transpose(im, Ls)));
-    up5(h->x1, pack2(x1p, x1m));
-    up5(h->x3, pack2(transpose(x1p, Ls), transpose(x1m, Ls)));
+    up5(h->m5inv, chain_coefs(Ls, h->alpha5, h->beta5, p->mf, 0.0, 1.0));
+    up5(h->x1, chain_coefs(Ls, h->alpha5, h->beta5, p->mf, p->c / p->b, p->b));
     HIPCHK(hipStreamSynchronize(st));
   });
   if (rc == MSPCG_OK) *hp = h.release();
@@ -1294,8 +1249,9 @@ mspcg_status m5inv(mspcg_handle *h, mspcg_field *out, const mspcg_field *in, int
     a.out = out->data;
     a.out_norm = out->norm;
     a.stride = h->Vh;
-    a.dense = 1;
-    a.mat = dagger ? h->m5inv_t.ptr(in->prec) : h->m5inv.ptr(in->prec);
+    a.inv = 1;
+    a.dag = dagger ? 1 : 0;
+    a.chain = h->m5inv.ptr(in->prec);
     HIPCHK(launch_op5(in->prec, a, S(stream)));
   });
 }
@@ -1438,14 +1394,14 @@ mspcg_status dwf_prepare_rhs(mspcg_handle *h, mspcg_field *b, const mspcg_field 
     a.in = phi_o->data;
     a.out = to.data;
     a.stride = h->Vh;
-    a.dense = 1;
-    a.mat = h->m5inv.ptr(MSPCG_F64);
+    a.inv = 1;
+    a.chain = h->m5inv.ptr(MSPCG_F64);
     HIPCHK(launch_op5(MSPCG_F64, a, st));
     // te = M^4_eo t_o ; phihat = phi_e - te (into te)
     global_hop(h, MSPCG_F64, nrhs, 0, te, to, 0, 1, EPI_SCALE, -0.5, nullptr, nullptr, nullptr, nullptr, st);
     HIPCHK(blas_axpby((double *)te.data, 1.0, (const double *)phi_e->data, -1.0, (const double *)te.data, n, nrhs, st));
     // b = D_PC^+ phihat
-    global_hop(h, MSPCG_F64, nrhs, 1, to, te, 1, 0, EPI_DENSE, -0.5, &h->x3, nullptr, nullptr, nullptr,
+    global_hop(h, MSPCG_F64, nrhs, 1, to, te, 1, 0, EPI_M5INV, -0.5, &h->x1, nullptr, nullptr, nullptr,
                st);
     global_hop(h, MSPCG_F64, nrhs, 0, vec_of(h, b), to, 1, 0, EPI_M5DAG_MPHIDAG, 0.5, nullptr, &te, nullptr, nullptr,
                st);
@@ -1482,8 +1438,8 @@ mspcg_status dwf_reconstruct(mspcg_handle *h, mspcg_field *psi_o, const mspcg_fi
     a.in = to.data;
     a.out = psi_o->data;
     a.stride = h->Vh;
-    a.dense = 1;
-    a.mat = h->m5inv.ptr(MSPCG_F64);
+    a.inv = 1;
+    a.chain = h->m5inv.ptr(MSPCG_F64);
     HIPCHK(launch_op5(MSPCG_F64, a, st));
     HIPCHK(hipStreamSynchronize(st));
   });

@@ -9,10 +9,17 @@
 
 namespace mspcg {
 
+// A fifth-dimension operator X = sigma (1 + rho S)(1 - q S)^{-1} per chirality
+// (S the chirality's shift of P_chi) is passed to the kernels as its chain
+// coefficients [rho, -rho mf, q, sigma, lambda_0 .. lambda_{Ls-1}],
+// lambda_i = gamma q^i, gamma = -q mf / (1 + mf q^Ls); the kernels apply it
+// as a recurrence along s.
+constexpr int kChainHead = 4;
+
 // Epilogues of the hop kernel (what is written for each output 5D site):
 enum Epi {
   EPI_SCALE = 0,          // out = scale * hop
-  EPI_DENSE = 1,          // out = scale * X hop, X a real Ls x Ls matrix per chirality
+  EPI_M5INV = 1,          // out = scale * X hop, X = M_phi M_5^{-1} (undaggered hop) or its transpose (daggered)
   EPI_MPHIDAG = 2,        // out = scale * M_phi^+ hop
   EPI_M5_OTHER = 3,       // out = M_5 other + scale * hop
   EPI_M5DAG_MPHIDAG = 4,  // out = M_5^+ other + scale * M_phi^+ hop
@@ -47,7 +54,7 @@ struct HopArgs {
   const int *other_idx;  // output list position -> index in `other`, -1 outside (zero); nullptr: identity
   int other_zero;        // zero site of `other` (inactive threads)
   double scale;
-  const void *mat;     // EPI_DENSE: [2][Ls][Ls] row-major (chirality +, then -) in the compute type
+  const void *mat;     // EPI_M5INV: chain coefficients of X (kChainHead + Ls values in the compute type)
   double mphi_b, mphi_c, mf, m5_alpha, m5_beta;
   double *partial;     // DOT: [gridDim.x][nrhs] partial sums of Re<w, out>
   const void *dotw;
@@ -65,7 +72,8 @@ int hop_groups_per_wave(int Ls, int nrhs);
 hipError_t launch_hop(int prec, int dagger, int pre_mphi, int epi, int dot, int global, const HopArgs &a,
                       hipStream_t st);
 
-// out = X in on a site list (identity list), X = a + b P_chi (dag: P_chi^+) or a dense chiral matrix.
+// out = X in on a site list (identity list), X = a + b P_chi (dag: P_chi^+) or, with inv,
+// M_5^{-1} (dag: its transpose) from chain coefficients.
 struct Op5Args {
   int nsites, Ls, nrhs, nsite_wg;
   const void *in;
@@ -73,8 +81,8 @@ struct Op5Args {
   void *out;
   float *out_norm;
   long long stride;
-  int dense;            // 1: use mat; 0: a + b P_chi
-  const void *mat;      // [2][Ls][Ls] row-major in the compute type
+  int inv;              // 1: use chain; 0: a + b P_chi
+  const void *chain;    // chain coefficients of M_5^{-1} (kChainHead + Ls values in the compute type)
   double a, b, mf;
   int dag;
 };

@@ -313,162 +313,109 @@ __device__ inline void hop_dir_h16(float *lds, int nthr, int tid, int s, int Ls,
   hop_half_h16<MU, SGN>(h, U, acc, m);
 }
 
-// ---------------------------------------------------------------- dense fifth-dimension matrices
-// v <- scale * X v, X a real Ls x Ls matrix per chirality (rows s, columns t;
-// chirality + acts on reals 0..11, chirality - on 12..23).  The Ls values of
-// one 4D site and right-hand side live on Ls consecutive lanes, so per
-// chirality this is X (Ls x Ls) times a (Ls x 12 n_groups) matrix: a dense
-// contraction that runs on the matrix cores (16x16x4 MFMA, FP32 or FP64
-// operands).  Needs a multiple of 64 threads and Ls % 4 == 0; otherwise the
-// VALU loop below is used.
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-template <typename R> struct V4;
-template <> struct V4<float> { using T = f32x4; };
-template <> struct V4<double> { using T = f64x4; };
-__device__ inline f32x4 mfma16x16x4(float a, float b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-__device__ inline f64x4 mfma16x16x4(double a, double b, f64x4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
+// ---------------------------------------------------------------- M_5^{-1} along the fifth dimension
+// v <- scale X v per chirality for X = sigma (1 + rho S)(1 - q S)^{-1}, S the
+// chirality's shift of P_chi (chirality +, reals 0..11: s takes s-1; chirality
+// -, reals 12..23: s takes s+1; S^Ls = -mf), or X^T (TR = 1: the shift runs the
+// other way).  With sigma = b / alpha, rho = c / b and q = beta / alpha this is
+// M_phi M_5^{-1} = (b + c P_chi)(alpha - beta P_chi)^{-1}; with rho = 0 and
+// sigma = 1 / alpha it is M_5^{-1} alone (M_5 = alpha - beta P_chi, Eq. (5)).
+// Both factors are functions of S, so X v is a first-order recurrence along s
+// instead of a dense Ls x Ls product: with positions i counted along the shift
+// (i = s, or Ls - 1 - s where the shift takes s+1),
+//   u_0 = x_0 + wrap x_{Ls-1},  u_i = x_i + rho x_{i-1}          ((1 + rho S) x)
+//   z_0 = u_0,                  z_i = u_i + q z_{i-1}            (no wrap-around)
+//   (X x)_i = sigma (z_i + lambda_i z_{Ls-1})
+// where wrap = -rho mf and lambda_i = gamma q^i, gamma = -q mf / (1 + mf q^Ls),
+// restores the -mf corner of S (exact: (1 - q S)^{-1} = sum_k q^k S^k / (1 + mf q^Ls)).
+// cf = [rho, wrap, q, sigma, lambda_0 .. lambda_{Ls-1}] in the compute type.
+//
+// The Ls values of one (site, rhs) sit on the Ls consecutive threads of its
+// group; they are transposed through LDS (rows = positions i, one row of
+// kChainStride words per thread: an odd stride, so a row store of all lanes
+// and a column load of all lanes both spread over the banks), lane t of the
+// group runs the recurrence of columns t, t + Ls, ... < 24, and the rows are
+// read back.  A chirality whose shift takes s+1 is stored with its rows
+// reversed, so every column runs toward increasing i.
+constexpr int kChainStride = 25;
 
-// lds: [24][nthr] structure of arrays; X: [2][Ls][Ls] (LDS copy); G: the lane
-// layout (groups per wave, 0: dense).  Lane l of a wave supplies A[l%16][l/16]
-// and B[l/16][l%16] and receives four entries of column l%16 of D.
-template <typename R>
-__device__ inline void dense_chiral(R *lds, const R *X, int nthr, int tid, int s, int Ls, int ngroups, int G, R scale,
-                                   R v[24], bool lds_in_use) {
-  if (lds_in_use) __syncthreads();  // earlier exchanges through the same LDS words
-#pragma unroll
-  for (int k = 0; k < 24; ++k) lds[k * nthr + tid] = v[k];
-  __syncthreads();
-  if ((nthr & 63) == 0 && (Ls & 3) == 0 && Ls <= 32) {
-    using T4 = typename V4<R>::T;
-    const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
-    const int row = lane & 15, kq = lane >> 4;
-    const int ncol = ngroups * 12;
-    const int ntn = (ncol + 15) >> 4;
-    for (int task = wave; task < 2 * ntn; task += nwaves) {
-      const int chi = task / ntn, nt = task - chi * ntn;
-      const int col = nt * 16 + row;
-      const bool colok = col < ncol;
-      const int g = colok ? col / 12 : 0;
-      const int comp = chi * 12 + (colok ? col - 12 * g : 0);
-      const R *Xc = X + chi * Ls * Ls;
-      T4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
-      for (int k0 = 0; k0 < Ls; k0 += 4) {
-        const int t = k0 + kq;
-        const R b = colok ? lds[comp * nthr + group_tid(G, Ls, g, t)] : R(0);
-        const R a0 = (row < Ls) ? Xc[row * Ls + t] : R(0);
-        c0 = mfma16x16x4(a0, b, c0);
-        if (Ls > 16) {
-          const R a1 = (16 + row < Ls) ? Xc[(16 + row) * Ls + t] : R(0);
-          c1 = mfma16x16x4(a1, b, c1);
-        }
-      }
-      if (colok) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          // output rows of the 16x16x4 MFMA: FP32 puts rows 4(l/16)+i in lane l's
-          // four results, FP64 rows 4i + l/16
-          const int m = (sizeof(R) == 8) ? 4 * i + kq : 4 * kq + i;
-          if (m < Ls) lds[comp * nthr + group_tid(G, Ls, g, m)] = scale * c0[i];
-          if (Ls > 16 && 16 + m < Ls) lds[comp * nthr + group_tid(G, Ls, g, 16 + m)] = scale * c1[i];
-        }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 24; ++k) v[k] = lds[k * nthr + tid];
-  } else {
-    const int g0 = tid - s;
-    R o[24];
-    zero24(o);
-    for (int t = 0; t < Ls; ++t) {
-      const R mp = X[s * Ls + t];
-      const R mm = X[Ls * Ls + s * Ls + t];
-#pragma unroll
-      for (int k = 0; k < 12; ++k) o[k] += mp * lds[k * nthr + g0 + t];
-#pragma unroll
-      for (int k = 12; k < 24; ++k) o[k] += mm * lds[k * nthr + g0 + t];
-    }
-#pragma unroll
-    for (int k = 0; k < 24; ++k) v[k] = scale * o[k];
-  }
-}
-
-// The same contraction where every wave holds whole (site, rhs) groups (the
-// DPP and ds_bpermute layouts: G groups of Ls lanes per wave): each wave
-// contracts only its own groups' columns, in its own slice of the LDS
-// structure of arrays, so no workgroup barrier is needed.  Lanes read words
-// that other lanes of the same wave wrote: wave_lds_sync between the stores
-// and those loads keeps the compiler from moving one across the other (the
-// hardware serves one wave's LDS accesses in order).  Per chirality the wave's 12 G columns
-// form ceil(12 G / 16) MFMA tiles; the X operand of a lane is the same for
-// every tile and is read once.  Needs Ls % 4 == 0 and Ls <= 32; X must be
-// visible to all waves (staged before a barrier).  LSC > 0 fixes Ls at
-// compile time (straight-line code for the common lengths), 0 reads it from Ls.
 template <typename R, int LSC>
-__device__ inline void dense_chiral_wave_t(R *lds, const R *X, int nthr, int tid, int Ls_rt, R scale, R v[24]) {
-  using T4 = typename V4<R>::T;
+__device__ inline void chain_columns(R *Tg, int t, int Ls_rt, const R *cf, R sig) {
   const int Ls = LSC > 0 ? LSC : Ls_rt;
-  const int G = 64 / Ls;
-  const int lane = tid & 63;
-  R *W = lds + (tid - lane);  // component k of the wave's lane j: W[k * nthr + j]
+  const R rho = cf[0], wrap = cf[1], q = cf[2];
+  for (int k = t; k < 24; k += Ls) {
+    R *c = Tg + k;
+    if constexpr (LSC > 0) {  // the column in registers
+      R x[LSC];
 #pragma unroll
-  for (int k = 0; k < 24; ++k) W[k * nthr + lane] = v[k];
-  wave_lds_sync();
-  const int row = lane & 15, kq = lane >> 4;
-  const int ncol = 12 * G, ntn = (ncol + 15) >> 4, nk = Ls >> 2;
+      for (int i = 0; i < LSC; ++i) x[i] = c[i * kChainStride];
+      R prev = x[0];
+      x[0] = fma(wrap, x[LSC - 1], x[0]);
 #pragma unroll
-  for (int chi = 0; chi < 2; ++chi) {
-    const R *Xc = X + chi * Ls * Ls;
-    R a0[8], a1[8];  // X[row][4 j + kq] and X[16 + row][4 j + kq], j < Ls / 4
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      a0[j] = (j < nk && row < Ls) ? Xc[row * Ls + 4 * j + kq] : R(0);
-      a1[j] = (j < nk && 16 + row < Ls) ? Xc[(16 + row) * Ls + 4 * j + kq] : R(0);
-    }
-    for (int nt = 0; nt < ntn; ++nt) {
-      const int col = nt * 16 + row;
-      const bool colok = col < ncol;
-      const int gi = colok ? col / 12 : 0;
-      R *Wc = W + (chi * 12 + (colok ? col - 12 * gi : 0)) * nthr + gi * Ls;
-      T4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        if (j < nk) {
-          const R b = colok ? Wc[4 * j + kq] : R(0);
-          c0 = mfma16x16x4(a0[j], b, c0);
-          if (Ls > 16) c1 = mfma16x16x4(a1[j], b, c1);
-        }
+      for (int i = 1; i < LSC; ++i) {
+        const R cur = x[i];
+        x[i] = fma(q, x[i - 1], fma(rho, prev, cur));
+        prev = cur;
       }
-      if (colok) {
+      const R zl = x[LSC - 1];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          // output rows: FP32 4(l/16) + i, FP64 4i + l/16 (as in dense_chiral)
-          const int m = (sizeof(R) == 8) ? 4 * i + kq : 4 * kq + i;
-          if (m < Ls) Wc[m] = scale * c0[i];
-          if (Ls > 16 && 16 + m < Ls) Wc[16 + m] = scale * c1[i];
-        }
+      for (int i = 0; i < LSC; ++i) c[i * kChainStride] = sig * fma(cf[4 + i], zl, x[i]);
+    } else {  // any Ls: in place in LDS
+      R prev = c[0];
+      R z = fma(wrap, c[(Ls - 1) * kChainStride], prev);
+      c[0] = z;
+      for (int i = 1; i < Ls; ++i) {
+        const R cur = c[i * kChainStride];
+        z = fma(q, z, fma(rho, prev, cur));
+        c[i * kChainStride] = z;
+        prev = cur;
       }
-      wave_lds_sync();
+      for (int i = 0; i < Ls; ++i) c[i * kChainStride] = sig * fma(cf[4 + i], z, c[i * kChainStride]);
     }
   }
-#pragma unroll
-  for (int k = 0; k < 24; ++k) v[k] = W[k * nthr + lane];
 }
-template <typename R>
-__device__ inline void dense_chiral_wave(R *lds, const R *X, int nthr, int tid, int Ls, R scale, R v[24]) {
-  if (Ls == 16)
-    dense_chiral_wave_t<R, 16>(lds, X, nthr, tid, Ls, scale, v);
-  else if (Ls == 12)
-    dense_chiral_wave_t<R, 12>(lds, X, nthr, tid, Ls, scale, v);
-  else if (Ls == 8)
-    dense_chiral_wave_t<R, 8>(lds, X, nthr, tid, Ls, scale, v);
-  else
-    dense_chiral_wave_t<R, 0>(lds, X, nthr, tid, Ls, scale, v);
+
+// lds: kChainStride * nthr values; G: groups per wave of the lane layout (0:
+// dense packing, groups may straddle waves: workgroup barriers; otherwise the
+// groups of a wave only touch that wave's rows).  Must be reached by all
+// threads of the workgroup.
+template <int TR, typename R, int LSC>
+__device__ inline void m5_chain_t(R *lds, int tid, int s, int Ls_rt, int G, const R *cf, R scale, R v[24]) {
+  const int Ls = LSC > 0 ? LSC : Ls_rt;
+  R *Tg = lds + (size_t)(tid - s) * kChainStride;  // this group's rows
+  const int rp = TR ? Ls - 1 - s : s;              // row of chirality + (reals 0..11)
+  const int rm = TR ? s : Ls - 1 - s;              // row of chirality -
+  // The idle lanes past a wave's last whole group (whole-wave layouts) form
+  // no group: their rows would run into the next wave's, so they take no part.
+  const bool own = G == 0 || ((tid & 63) - s) + Ls <= 64;
+  if (G == 0) __syncthreads();                     // (earlier exchanges through the same words)
+  if (own) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) Tg[rp * kChainStride + k] = v[k];
+#pragma unroll
+    for (int k = 12; k < 24; ++k) Tg[rm * kChainStride + k] = v[k];
+  }
+  if (G == 0) __syncthreads(); else wave_lds_sync();
+  if (own) chain_columns<R, LSC>(Tg, s, Ls, cf, cf[3] * scale);
+  if (G == 0) __syncthreads(); else wave_lds_sync();
+  if (own) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = Tg[rp * kChainStride + k];
+#pragma unroll
+    for (int k = 12; k < 24; ++k) v[k] = Tg[rm * kChainStride + k];
+  }
+}
+
+template <int TR, typename R>
+__device__ inline void m5_chain(R *lds, int tid, int s, int Ls, int G, const R *cf, R scale, R v[24]) {
+  switch (Ls) {
+    case 8: m5_chain_t<TR, R, 8>(lds, tid, s, Ls, G, cf, scale, v); break;
+    case 12: m5_chain_t<TR, R, 12>(lds, tid, s, Ls, G, cf, scale, v); break;
+    case 16: m5_chain_t<TR, R, 16>(lds, tid, s, Ls, G, cf, scale, v); break;
+    case 24: m5_chain_t<TR, R, 24>(lds, tid, s, Ls, G, cf, scale, v); break;
+    case 32: m5_chain_t<TR, R, 32>(lds, tid, s, Ls, G, cf, scale, v); break;
+    default: m5_chain_t<TR, R, 0>(lds, tid, s, Ls, G, cf, scale, v); break;
+  }
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
@@ -540,8 +487,7 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
     sl = g / nrhs;
   }
   R *Lk = reinterpret_cast<R *>(smem);  // [nsite_wg][8][18] links of this workgroup's sites
-  R *Xl = Lk + nsw * 144;               // [2][Ls][Ls] dense epilogue matrix
-  R *lds = Xl + (EPI == EPI_DENSE ? 2 * Ls * Ls : 0);  // [24][nthr] exchanges (LDS mode, dense epilogue)
+  R *lds = Lk + nsw * 144;              // exchanges: [24][nthr] (LDS mode), [nthr][kChainStride] (M_5^{-1})
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int site = tile * nsw + sl;
   const int cbr = (site < a.nsites) ? a.site_cb[site] : -1;
@@ -593,10 +539,6 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
       else
         widen16<R>(src + c * per, Lk + sl * 144 + c * per);
     }
-  }
-  if (EPI == EPI_DENSE) {
-    const R *Xg = reinterpret_cast<const R *>(a.mat);
-    for (int i = tid; i < 2 * Ls * Ls; i += nthr) Xl[i] = Xg[i];
   }
   __syncthreads();
 
@@ -665,11 +607,8 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
   }
 
   const R scale = (R)(PRE ? a.scale * a.mphi_b : a.scale);
-  if (EPI == EPI_DENSE) {
-    if (XM != kXLds && (Ls & 3) == 0 && Ls <= 32)
-      dense_chiral_wave<R>(lds, Xl, nthr, tid, Ls, scale, acc);
-    else
-      dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * nsw, G, scale, acc, XM == kXLds);
+  if (EPI == EPI_M5INV) {
+    m5_chain<DAG, R>(lds, tid, s, Ls, G, reinterpret_cast<const R *>(a.mat), scale, acc);
   } else if (EPI == EPI_MPHIDAG || EPI == EPI_M5DAG_MPHIDAG) {
     pchi_comb<1, XM, R>(lds, nthr, tid, s, Ls, (R)a.mphi_b, (R)a.mphi_c, (R)a.mf, acc);
 #pragma unroll
@@ -711,8 +650,8 @@ template <typename S>
 static size_t hop_lds_bytes(const HopArgs &a, int nthr, int epi, int dot, int xm) {
   using R = typename Traits<S>::R;
   size_t b = (size_t)144 * a.nsite_wg * sizeof(R);
-  if (epi == EPI_DENSE) b += (size_t)2 * a.Ls * a.Ls * sizeof(R);
-  if (epi == EPI_DENSE || xm == kXLds) b += (size_t)24 * nthr * sizeof(R);
+  if (epi == EPI_M5INV) b += (size_t)kChainStride * nthr * sizeof(R);
+  else if (xm == kXLds) b += (size_t)24 * nthr * sizeof(R);
   if (dot) b = std::max(b, (size_t)2 * nthr * sizeof(double));
   return b;
 }
@@ -744,16 +683,16 @@ static hipError_t dispatch_hop(int dagger, int pre, int epi, int dot, int global
     return launch_hop_t<S, D, P, E, T, G>(a, st);
   MSPCG_HOP(0, 1, EPI_SCALE, 0, 1)          // M^4 in
   MSPCG_HOP(1, 0, EPI_MPHIDAG, 0, 1)        // (M^4)^+ in
-  MSPCG_HOP(0, 1, EPI_DENSE, 0, 1)          // M_phi M_5^-1 M^4 in (first hop of D_PC)
+  MSPCG_HOP(0, 1, EPI_M5INV, 0, 1)          // M_phi M_5^-1 M^4 in (first hop of D_PC)
   MSPCG_HOP(0, 0, EPI_M5_OTHER, 0, 1)       // M_5 psi + 1/2 H c
-  MSPCG_HOP(1, 0, EPI_DENSE, 0, 1)          // M_5^-+ (M^4)^+ y
+  MSPCG_HOP(1, 0, EPI_M5INV, 0, 1)          // M_5^-+ M_phi^+ (M^4)^+ y
   MSPCG_HOP(1, 0, EPI_M5DAG_MPHIDAG, 0, 1)  // M_5^+ y + 1/2 M_phi^+ H^+ f
   MSPCG_HOP(1, 0, EPI_M5DAG_MPHIDAG, 1, 1)  //   ... with the fused <w, out>
-  MSPCG_HOP(0, 0, EPI_DENSE, 0, 0)          // the same four hops on block domains (M_phi p formed beforehand;
+  MSPCG_HOP(0, 0, EPI_M5INV, 0, 0)          // the same four hops on block domains (M_phi p formed beforehand;
                                             // neighbours outside a domain enter with weight zero, which needs
                                             // the input unmixed: no M_phi on the input there)
   MSPCG_HOP(0, 0, EPI_M5_OTHER, 0, 0)
-  MSPCG_HOP(1, 0, EPI_DENSE, 0, 0)
+  MSPCG_HOP(1, 0, EPI_M5INV, 0, 0)
   MSPCG_HOP(1, 0, EPI_M5DAG_MPHIDAG, 0, 0)
   MSPCG_HOP(1, 0, EPI_M5DAG_MPHIDAG, 1, 0)
 #undef MSPCG_HOP
@@ -794,23 +733,15 @@ __global__ void __launch_bounds__(256) op5_kernel(const Op5Args a) {
     sl = g / nrhs;
   }
   R *lds = reinterpret_cast<R *>(smem);
-  R *Xl = lds + 24 * nthr;
   const int site = blockIdx.x * a.nsite_wg + sl;
   const bool active = lane_ok && site < a.nsites;
-  constexpr bool kWave = XM != kXLds;
-  const bool wave_dense = kWave && (Ls & 3) == 0 && Ls <= 32;
   R v[24];
   const size_t idx = (size_t)r * a.stride + (active ? site : 0);
   load24<R>(reinterpret_cast<const S *>(a.in), a.in_norm, idx, s, Ls, v);
-  if (a.dense) {
-    const R *Xg = reinterpret_cast<const R *>(a.mat);
-    for (int i = tid; i < 2 * Ls * Ls; i += nthr) Xl[i] = Xg[i];
-    if (wave_dense) __syncthreads();  // (dense_chiral has its own barrier)
-  }
-  if (a.dense && wave_dense)
-    dense_chiral_wave<R>(lds, Xl, nthr, tid, Ls, R(1), v);
-  else if (a.dense)
-    dense_chiral<R>(lds, Xl, nthr, tid, s, Ls, nrhs * a.nsite_wg, G, R(1), v, false);
+  if (a.inv && a.dag)
+    m5_chain<1, R>(lds, tid, s, Ls, G, reinterpret_cast<const R *>(a.chain), R(1), v);
+  else if (a.inv)
+    m5_chain<0, R>(lds, tid, s, Ls, G, reinterpret_cast<const R *>(a.chain), R(1), v);
   else if (a.dag)
     pchi_comb<1, XM, R>(lds, nthr, tid, s, Ls, (R)a.a, (R)a.b, (R)a.mf, v);
   else
@@ -833,7 +764,7 @@ hipError_t launch_op5(int prec, const Op5Args &a, hipStream_t st) {
   const int grid = (a.nsites + a.nsite_wg - 1) / a.nsite_wg;
   if (a.nsite_wg < 1 || nthr > 256 || grid < 1) return hipErrorInvalidValue;
   const size_t rsz = (prec == MSPCG_F64) ? 8 : 4;
-  const size_t lds = (24 * (size_t)nthr + 2 * (size_t)a.Ls * a.Ls) * rsz;
+  const size_t lds = (size_t)kChainStride * nthr * rsz;
   const dim3 blk = (xm == kXLds) ? dim3(a.Ls, a.nrhs, a.nsite_wg) : dim3(nthr);
   switch (prec) {
     case MSPCG_F64: launch_op5_t<double>(a, dim3(grid), blk, lds, st); break;
