@@ -195,6 +195,11 @@ template <> struct RawSite<double> {
 #pragma unroll
     for (int k = 0; k < 12; ++k) c[k] = *reinterpret_cast<const double2 *>(base + chunk_index<double>(site4, s, Ls, k));
   }
+  // p: chunk 0 of the value, cs: the chunk stride (elements)
+  __device__ void load_at(const double *p, size_t cs, const float *) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) c[k] = *reinterpret_cast<const double2 *>(p + k * cs);
+  }
   template <typename R> __device__ void decode(R v[24]) const {
 #pragma unroll
     for (int k = 0; k < 12; ++k) { v[2 * k] = (R)c[k].x; v[2 * k + 1] = (R)c[k].y; }
@@ -205,6 +210,10 @@ template <> struct RawSite<float> {
   __device__ void load(const float *base, const float *, size_t site4, int s, int Ls) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) c[k] = *reinterpret_cast<const float4 *>(base + chunk_index<float>(site4, s, Ls, k));
+  }
+  __device__ void load_at(const float *p, size_t cs, const float *) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) c[k] = *reinterpret_cast<const float4 *>(p + k * cs);
   }
   template <typename R> __device__ void decode(R v[24]) const {
 #pragma unroll
@@ -236,6 +245,11 @@ template <> struct RawSite<_Float16> {
 #pragma unroll
     for (int k = 0; k < 3; ++k) c[k] = *reinterpret_cast<const uint4 *>(base + chunk_index<_Float16>(site4, s, Ls, k));
   }
+  __device__ void load_at(const _Float16 *p, size_t cs, const float *np) {
+    n = *np;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c[k] = *reinterpret_cast<const uint4 *>(p + k * cs);
+  }
 };
 template <> struct RawSite<bf16> {
   uint4 c[3];
@@ -256,6 +270,11 @@ template <> struct RawSite<bf16> {
     n = norm[site4 * Ls + s];
 #pragma unroll
     for (int k = 0; k < 3; ++k) c[k] = *reinterpret_cast<const uint4 *>(base + chunk_index<bf16>(site4, s, Ls, k));
+  }
+  __device__ void load_at(const bf16 *p, size_t cs, const float *np) {
+    n = *np;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c[k] = *reinterpret_cast<const uint4 *>(p + k * cs);
   }
 };
 
@@ -438,6 +457,15 @@ __device__ inline void link_pairs_h16(uint4 q, uint32_t *o) {
   }
 }
 
+// a.x b.x + a.y b.y in FP32 (exact products).  Written as the three-operand
+// form with a zero addend: the compiler's own choice for a zero start, the
+// accumulating two-operand form, needs a separate move of 0 into the result.
+__device__ inline float dot2_from_zero(half2_t a, half2_t b) {
+  float r;
+  asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 // hop_half for packed F16 half spinors: acc += n (U h, -SGN B^+ U h), U as
 // staged pairs (18 words, row-major), one colour row at a time
 template <int MU, int SGN>
@@ -450,9 +478,10 @@ __device__ inline void hop_half_h16(const half2_t h[6], const uint32_t *U, float
     float w[4];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      float re = 0.f, im = 0.f;
+      float re = dot2_from_zero(as_half2(ur[0]), h[3 * k]);
+      float im = dot2_from_zero(as_half2(ur[1]), h[3 * k]);
 #pragma unroll
-      for (int b = 0; b < 3; ++b) {
+      for (int b = 1; b < 3; ++b) {
         re = __builtin_amdgcn_fdot2(as_half2(ur[2 * b]), h[3 * k + b], re, false);
         im = __builtin_amdgcn_fdot2(as_half2(ur[2 * b + 1]), h[3 * k + b], im, false);
       }

@@ -130,6 +130,46 @@ __device__ inline void pchi_comb(R *lds, int nthr, int tid, int s, int Ls, R a, 
   }
 }
 
+// A <- A + P_chi B (DAG = 0) or A + P_chi^+ B (DAG = 1) on the Ls column held one
+// s per lane (the directions and corners of pchi_comb): one exchange for a
+// combination a u + b P u + c w + d P w of two columns.  Must be reached by
+// all threads of the workgroup.
+template <int DAG, int XM, typename R>
+__device__ inline void pchi_add(R *lds, int nthr, int tid, int s, int Ls, R mf, R A[24], const R B[24]) {
+  const R cm = (s > 0) ? R(1) : -mf;
+  const R cp = (s < Ls - 1) ? R(1) : -mf;
+  const R cu = DAG ? cp : cm;
+  const R cl = DAG ? cm : cp;
+  if (XM == kXDpp16) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) A[k] += cu * (DAG ? rot_next_dpp(B[k]) : rot_prev_dpp(B[k]));
+#pragma unroll
+    for (int k = 12; k < 24; ++k) A[k] += cl * (DAG ? rot_prev_dpp(B[k]) : rot_next_dpp(B[k]));
+  } else if (XM == kXPerm) {
+    const int lane = tid & 63;
+    const int am = 4 * ((s > 0) ? lane - 1 : lane + Ls - 1);
+    const int ap = 4 * ((s < Ls - 1) ? lane + 1 : lane - (Ls - 1));
+    const int au = DAG ? ap : am, al = DAG ? am : ap;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) A[k] += cu * perm(au, B[k]);
+#pragma unroll
+    for (int k = 12; k < 24; ++k) A[k] += cl * perm(al, B[k]);
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 24; ++k) lds[k * nthr + tid] = B[k];
+    __syncthreads();
+    const int tm = (s > 0) ? tid - 1 : tid + Ls - 1;
+    const int tp = (s < Ls - 1) ? tid + 1 : tid - (Ls - 1);
+    const int tu = DAG ? tp : tm;
+    const int tl = DAG ? tm : tp;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) A[k] += cu * lds[k * nthr + tu];
+#pragma unroll
+    for (int k = 12; k < 24; ++k) A[k] += cl * lds[k * nthr + tl];
+  }
+}
+
 // Projected half spinor of (1 + pc P_chi) v for the hop in direction MU:
 // h(s) = X(s) + Y(s) + cu X(s-1) + cl Y(s+1) with X, Y the two parts of the
 // projection (P_chi takes the upper spins from s-1 and the lower ones from
@@ -520,8 +560,19 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
   // the first neighbour spinor is requested before anything else waits
   const S *in = reinterpret_cast<const S *>(a.in);
   const size_t rin = (size_t)r * a.in_stride;
+  // neighbour n of this lane: chunk 0 at in_s + n * sstride, its chunks cstride
+  // apart, its norm at nrm_s + n * Ls (one multiply-add per address)
+  // (32 x 32 -> 64-bit products: one multiply-add each)
+  const S *in_s = in + chunk_index<S>(rin, s, Ls, 0);
+  const uint32_t cstride = (uint32_t)Ls * Chunk<S>::kReals;
+  const uint32_t sstride = cstride * Chunk<S>::kCount;
+  const float *nrm_s = Traits<S>::kNorm ? a.in_norm + rin * Ls + s : nullptr;
+  auto load_nbr = [&](RawSite<S> &dst, int n) {
+    const uint64_t un = (uint32_t)n;
+    dst.load_at(in_s + un * sstride, cstride, Traits<S>::kNorm ? nrm_s + un * (uint32_t)Ls : nullptr);
+  };
   RawSite<S> cur, nxt;
-  cur.load(in, a.in_norm, rin + nbw[0], s, Ls);
+  load_nbr(cur, nbw[0]);
 
   // the links of all sites of the workgroup, staged once into LDS with
   // 16-byte loads (every link is used by all Ls x nrhs lanes of its site);
@@ -563,15 +614,15 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
   // (nbw[0], nbw[1]) always hold the indices of directions 2 mu, 2 mu + 1
 #pragma unroll 1
   for (int mu = 0; mu < 4; ++mu) {
-    if (kPrefetch) nxt.load(in, a.in_norm, rin + nbw[1], s, Ls);
+    if (kPrefetch) load_nbr(nxt, nbw[1]);
 #pragma unroll
     for (int bw = 0; bw < 2; ++bw) {
       const int d = 2 * mu + bw;
       // (unconditional: after the last pair nbw[2] is direction 6 again, a
       // cached reload; a load skipped on one path would make the wait
       // before the backward direction drain every load in flight)
-      if (kPrefetch && bw == 1) cur.load(in, a.in_norm, rin + nbw[2], s, Ls);
-      if (!kPrefetch && d > 0) cur.load(in, a.in_norm, rin + nbw[bw], s, Ls);
+      if (kPrefetch && bw == 1) load_nbr(cur, nbw[2]);
+      if (!kPrefetch && d > 0) load_nbr(cur, nbw[bw]);
       const R *U = Lsite + d * 18;
       // (1 - g_mu) for the forward hop of H and the backward hop of H^+
       constexpr int sp = (DAG != 0) ? -1 : 1;
@@ -609,11 +660,11 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
   const R scale = (R)(PRE ? a.scale * a.mphi_b : a.scale);
   if (EPI == EPI_M5INV) {
     m5_chain<DAG, R>(lds, tid, s, Ls, G, reinterpret_cast<const R *>(a.mat), scale, acc);
-  } else if (EPI == EPI_MPHIDAG || EPI == EPI_M5DAG_MPHIDAG) {
+  } else if (EPI == EPI_MPHIDAG) {
     pchi_comb<1, XM, R>(lds, nthr, tid, s, Ls, (R)a.mphi_b, (R)a.mphi_c, (R)a.mf, acc);
 #pragma unroll
     for (int k = 0; k < 24; ++k) acc[k] *= scale;
-  } else {
+  } else if (EPI == EPI_SCALE) {
 #pragma unroll
     for (int k = 0; k < 24; ++k) acc[k] *= scale;
   }
@@ -623,11 +674,19 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
     zero24(o);
     if (oi >= 0)  // (outside the block domain the operand vanishes)
       load24<R>(reinterpret_cast<const S *>(a.other), a.other_norm, (size_t)r * a.other_stride + oi, s, Ls, o);
-    // M_5 = alpha - beta P_chi ; M_5^+ = alpha - beta P_chi^+
-    pchi_comb<EPI == EPI_M5DAG_MPHIDAG ? 1 : 0, XM, R>(lds, nthr, tid, s, Ls, (R)a.m5_alpha, (R)(-a.m5_beta), (R)a.mf,
-                                                     o);
+    // M_5 = alpha - beta P_chi, M_5^+ = alpha - beta P_chi^+, M_phi^+ = b + c P_chi^+:
+    //   M_5 o + scale h                 = (alpha o + scale h) + P_chi (-beta o)
+    //   M_5^+ o + scale M_phi^+ h       = (alpha o + scale b h) + P_chi^+ (-beta o + scale c h)
+    const R al = (R)a.m5_alpha, mbe = (R)(-a.m5_beta);
+    const R sb = EPI == EPI_M5DAG_MPHIDAG ? scale * (R)a.mphi_b : scale;
+    const R sc = EPI == EPI_M5DAG_MPHIDAG ? scale * (R)a.mphi_c : R(0);
+    R B[24];
 #pragma unroll
-    for (int k = 0; k < 24; ++k) acc[k] += o[k];
+    for (int k = 0; k < 24; ++k) {
+      B[k] = fma(sc, acc[k], mbe * o[k]);
+      acc[k] = fma(sb, acc[k], al * o[k]);
+    }
+    pchi_add<EPI == EPI_M5DAG_MPHIDAG ? 1 : 0, XM, R>(lds, nthr, tid, s, Ls, (R)a.mf, acc, B);
   }
 
   if (active) store24<R>(reinterpret_cast<S *>(a.out), a.out_norm, (size_t)r * a.out_stride + self, s, Ls, acc);
