@@ -83,6 +83,7 @@ def time_dslash(h, A, w, prec, reps=50, warm=5):
     kernel is launched on, bracketing `reps` back-to-back launches."""
     import torch
 
+    torch.cuda.synchronize()  # (nothing else may run beside the timed launches)
     stream = torch.cuda.Stream()
     fin = h.field(prec, w.nrhs, 1)
     fout = h.field(prec, w.nrhs, 0)
@@ -107,6 +108,7 @@ def time_m5inv(h, A, w, prec, reps=50, warm=5):
     """Average duration of one m5inv launch (HIP events on the launch stream)."""
     import torch
 
+    torch.cuda.synchronize()
     stream = torch.cuda.Stream()
     fin = h.field(prec, w.nrhs, 1)
     fout = h.field(prec, w.nrhs, 1)
@@ -124,7 +126,8 @@ def time_m5inv(h, A, w, prec, reps=50, warm=5):
     ms = e0.elapsed_time(e1) / reps
     w_, n = BYTES[prec]
     bytes_ = 2 * (24 * w_ + n) * (A.V // 2) * w.Ls * w.nrhs
-    flops = 2 * 2 * 12 * w.Ls * w.Ls * (A.V // 2) * w.nrhs  # two chiralities, 12 columns each, Ls x Ls multiply-adds
+    # the recurrence along s: three multiply-adds and one multiply per real value
+    flops = 7 * 24 * w.Ls * (A.V // 2) * w.nrhs
     return {"us": ms * 1e3, "GB/s": bytes_ / (ms * 1e-3) / 1e9, "frac_hbm": bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "TFLOP/s": flops / (ms * 1e-3) / 1e12}
 
@@ -410,15 +413,21 @@ def study(w, torch, ks=(3, 4, 6, 8, 12, 18), inner_prec=None, snake_modes=(0, 1)
         for nsw in sweeps:
             for itol in inner_tols:
                 for k in ks:
+                    first = None
                     for rep in range(reps):  # the first solve of a shape tunes and captures
                         x.data.zero_()
                         st = h.mspcg_solve(x, b, w.nblk, k, prec, tol=w.tol, max_iter=max_iter,
                                            reliable=w.reliable, no_snake=no_snake, inner_tol=itol, n_sweeps=nsw)
+                        first = st["seconds"] if first is None else first
                     rows.append({"solver": "mspcg", "k": k, "snake_terms": not no_snake, "inner_tol": itol,
                                  "sweeps": nsw, "status": st["status"], "outer_iters": st["outer_iters"],
-                                 "seconds": st["seconds"], "true_rel_resid": st["true_rel_resid"]})
+                                 "inner_iters": st["inner_iters"], "seconds": st["seconds"],
+                                 "first_solve_seconds": first, "tuning_and_capture_s": first - st["seconds"],
+                                 "vs_cg": rows[0]["seconds"] / st["seconds"],
+                                 "true_rel_resid": st["true_rel_resid"]})
                     log(f"[study] k={k} snake={not no_snake} inner_tol={itol:g} sweeps={nsw}: "
-                        f"{st['outer_iters']} outer, {st['seconds']:.3f}s")
+                        f"{st['outer_iters']} outer, {st['seconds']:.3f}s (first solve {first:.3f}s), "
+                        f"{rows[0]['seconds'] / st['seconds']:.3f}x plain CG")
     print(json.dumps({"study": "inner iterations and snake terms", "workload": w.name,
                       "inner_prec": inner_prec or w.inner_prec, "blocks": list(w.nblk), "tol": w.tol, "rows": rows}),
           flush=True)

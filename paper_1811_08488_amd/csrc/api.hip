@@ -777,7 +777,12 @@ void run_block_cg(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int k, dou
   // inner_tol > 0: precision-based stopping (inner_stop.hip), else exactly k iterations
   const bool stop = inner_tol > 0.0;
   double *stopd = stop ? bg->stopbuf.as<double>() : nullptr;
-  HIPCHK(block_gather(prec, ba, bg->x.v, bg->r.v, bg->p.v, bg->mp.v, r, rr, n_total, part, st));
+  // Fixed k >= 1: x_0 = 0 is never stored (the first update sets x = alpha p)
+  // and the last iteration's x update happens in the scatter (x + alpha p,
+  // with no r update: nothing reads r after it).  Precision-based stopping
+  // keeps every step, since its test reads |r|^2 after the last update.
+  const bool lazy_x = !stop && k >= 1;
+  HIPCHK(block_gather(prec, ba, lazy_x ? Vec() : bg->x.v, bg->r.v, bg->p.v, bg->mp.v, r, rr, n_total, part, st));
   HIPCHK(block_scalars(2, ba, part, scal, st));
   if (stop) HIPCHK(inner_stop(0, bg->nb, nrhs, inner_tol, scal, stopd, st));
   for (int it = 0; it < k; ++it) {
@@ -790,12 +795,14 @@ void run_block_cg(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int k, dou
       HIPCHK(block_update_r(prec, ba, bg->r.v, bg->Ap.v, scal, part, st));
       HIPCHK(block_scalars(1, ba, part, scal, st));
       if (stop) HIPCHK(inner_stop(2, bg->nb, nrhs, inner_tol, scal, stopd, st));
-      HIPCHK(block_update_xp(prec, ba, bg->x.v, bg->p.v, bg->mp.v, bg->r.v, scal, st));
-    } else {
+      HIPCHK(block_update_xp(prec, ba, bg->x.v, bg->p.v, bg->mp.v, bg->r.v, scal, lazy_x && it == 0, st));
+    } else if (!lazy_x) {
       HIPCHK(block_update_xr(prec, ba, bg->x.v, bg->r.v, bg->p.v, bg->Ap.v, scal, part, st));
     }
   }
-  HIPCHK(block_scatter(prec, ba, z, bg->x.v, r, rr, n_total, partial_zr ? partial_zr : part, st));
+  const int smode = !lazy_x ? 0 : (k == 1 ? 2 : 1);
+  HIPCHK(block_scatter(prec, ba, z, bg->x.v, bg->p.v, scal, smode, r, rr, n_total, partial_zr ? partial_zr : part,
+                       st));
   if (nparts_zr) *nparts_zr = (ba.nsites + ba.nsite_wg - 1) / ba.nsite_wg;
 }
 
@@ -1147,7 +1154,13 @@ mspcg_status mspcg_create(mspcg_handle **hp, const mspcg_dwf *p, const double *g
     // kernels' workgroup renumbering) then need only a few neighbouring time
     // slices of one column at a time, which stay in that XCD's L2.
     int cdim[3];
-    for (int mu = 0; mu < 3; ++mu) cdim[mu] = (L[mu] % 8 == 0) ? 8 : L[mu];
+    for (int mu = 0; mu < 3; ++mu) cdim[mu] = (L[mu] % 12 == 0) ? 12 : (L[mu] % 8 == 0) ? 8 : L[mu];
+    if (const char *e = std::getenv("MSPCG_SITE_TILE")) {  // "x,y,z": spatial extent of the sweep's columns
+      int t[3];
+      if (std::sscanf(e, "%d,%d,%d", &t[0], &t[1], &t[2]) == 3 && t[0] > 0 && t[1] > 0 && t[2] > 0 &&
+          L[0] % t[0] == 0 && L[1] % t[1] == 0 && L[2] % t[2] == 0)
+        for (int mu = 0; mu < 3; ++mu) cdim[mu] = t[mu];
+    }
     for (int par = 0; par < 2; ++par) {
       std::vector<int> order;
       order.reserve(h->Vh);
@@ -1490,7 +1503,7 @@ mspcg_status mspcg_block_apply(mspcg_handle *h, mspcg_field *out, const mspcg_fi
     double *part = bg->partial.as<double>();
     HIPCHK(block_gather(prec, ba, bg->x.v, bg->r.v, bg->p.v, bg->mp.v, vec_of(h, in), nullptr, n_total, part, st));
     (void)block_hops(h, bg, prec, nrhs, bg->p.v, bg->mp.v, bg->Ap.v, nullptr, st);
-    HIPCHK(block_scatter(prec, ba, vec_of(h, out), bg->Ap.v, Vec(), nullptr, n_total, part, st));
+    HIPCHK(block_scatter(prec, ba, vec_of(h, out), bg->Ap.v, Vec(), nullptr, 0, Vec(), nullptr, n_total, part, st));
   });
 }
 

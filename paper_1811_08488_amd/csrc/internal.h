@@ -123,13 +123,17 @@ struct BlockArgs {
   const int *be_off;  // [nblocks+1] padded offsets (multiples of the block alignment, itself a multiple of 64)
   double mphi_b, mphi_c, mf;  // M_phi = b + c P_chi (the first block hop reads M_phi p, formed where p is)
 };
-// r_s = p_s = scale * r(cb), mp_s = M_phi p_s, x_s = 0; partial |r_s|^2 per workgroup.
+// r_s = p_s = scale * r(cb), mp_s = M_phi p_s, x_s = 0 (unless xs has no data);
+// partial |r_s|^2 per workgroup.
 // scale = sqrt(n_total/rr[rhs]).
 hipError_t block_gather(int prec, const BlockArgs &b, const Vec &xs, const Vec &rs, const Vec &ps, const Vec &mps,
                         const Vec &rglob, const double *rr, double n_total, double *partial, hipStream_t st);
-// z(cb) = x_s / scale; partial Re<z, r> per workgroup (FP64 r, z)
-hipError_t block_scatter(int prec, const BlockArgs &b, const Vec &zglob, const Vec &xs, const Vec &rglob,
-                         const double *rr, double n_total, double *partial, hipStream_t st);
+// z(cb) = v / scale with v = x_s (mode 0), x_s + alpha p_s (mode 1: the last
+// inner iteration's x update) or alpha p_s (mode 2: a single inner iteration);
+// partial Re<z, r> per workgroup (FP64 r, z)
+hipError_t block_scatter(int prec, const BlockArgs &b, const Vec &zglob, const Vec &xs, const Vec &ps,
+                         const double *scal, int mode, const Vec &rglob, const double *rr, double n_total,
+                         double *partial, hipStream_t st);
 // per (block, rhs): mode 0: alpha = rho/sum(partials) (0 if degenerate)
 //                   mode 1: rho_new = sum; beta = rho_new/rho (0 if rho = 0); rho = rho_new
 //                   mode 2: rho = sum (initialisation)
@@ -140,9 +144,10 @@ hipError_t block_update_xr(int prec, const BlockArgs &b, const Vec &x, const Vec
 // r -= alpha Ap, partial |r|^2 (the other inner iterations) ...
 hipError_t block_update_r(int prec, const BlockArgs &b, const Vec &r, const Vec &Ap, const double *scal,
                           double *partial, hipStream_t st);
-// ... then, once beta is known, x += alpha p, p = r + beta p and mp = M_phi p
+// ... then, once beta is known, x += alpha p (first: x = alpha p, x not read),
+// p = r + beta p and mp = M_phi p
 hipError_t block_update_xp(int prec, const BlockArgs &b, const Vec &x, const Vec &p, const Vec &mp, const Vec &r,
-                           const double *scal, hipStream_t st);
+                           const double *scal, int first, hipStream_t st);
 
 // scal layout per (block, rhs): [rho, alpha, beta, pad]
 constexpr int kScal = 4;

@@ -1053,9 +1053,11 @@ __global__ void __launch_bounds__(256) k_block_gather(const BlockArgs b, Vec xs,
     // the values as stored, so that r and p start identical and the sum matches them
     stored_values<S>(v);
     store24<R>(reinterpret_cast<S *>(ps.data), ps.norm, o, s, Ls, v);
-    R z[24];
-    zero24(z);
-    store24<R>(reinterpret_cast<S *>(xs.data), xs.norm, o, s, Ls, z);
+    if (xs.data) {  // (the fixed-k solve sets x in its first update instead)
+      R z[24];
+      zero24(z);
+      store24<R>(reinterpret_cast<S *>(xs.data), xs.norm, o, s, Ls, z);
+    }
     R acc = 0;
 #pragma unroll
     for (int k = 0; k < 24; ++k) acc += v[k] * v[k];
@@ -1068,8 +1070,8 @@ __global__ void __launch_bounds__(256) k_block_gather(const BlockArgs b, Vec xs,
 
 template <typename S>
 __global__ void __launch_bounds__(256) k_block_scatter(const BlockArgs b, double *zg, long long zg_stride, Vec xs,
-                                                        const double *rg, const double *rr, double n_total,
-                                                        double *partial) {
+                                                        Vec ps, const double *scal, int mode, const double *rg,
+                                                        const double *rr, double n_total, double *partial) {
   using R = typename Traits<S>::R;
   extern __shared__ __align__(16) unsigned char smem[];
   const int nthr = blockDim.x, tid = threadIdx.x, Ls = b.Ls, G = b.nrhs * Ls;
@@ -1079,8 +1081,17 @@ __global__ void __launch_bounds__(256) k_block_scatter(const BlockArgs b, double
   double val = 0;
   if (cb >= 0) {
     const double inv = rr ? (rr[r] > 0 ? sqrt(rr[r] / n_total) : 0.0) : 1.0;
+    const size_t o = (size_t)r * xs.stride + site;
     R v[24];
-    load24<R>(reinterpret_cast<const S *>(xs.data), xs.norm, (size_t)r * xs.stride + site, s, Ls, v);
+    if (mode == 2) zero24(v); else load24<R>(reinterpret_cast<const S *>(xs.data), xs.norm, o, s, Ls, v);
+    if (mode != 0) {  // the last inner iteration's x update, not stored: x + alpha p
+      const int blk = b.be_blk[site];
+      const R al = (R)scal[((size_t)blk * b.nrhs + r) * kScal + 1];
+      R pv[24];
+      load24<R>(reinterpret_cast<const S *>(ps.data), ps.norm, o, s, Ls, pv);
+#pragma unroll
+      for (int k = 0; k < 24; ++k) v[k] = fma(al, pv[k], v[k]);
+    }
     double z[24], t[24];
 #pragma unroll
     for (int k = 0; k < 24; ++k) z[k] = inv * (double)v[k];
@@ -1165,7 +1176,7 @@ __global__ void __launch_bounds__(256) k_block_update_r(const BlockArgs b, Vec r
 // values as stored)
 template <typename S>
 __global__ void __launch_bounds__(256) k_block_update_xp(const BlockArgs b, Vec xv, Vec pv, Vec mpv, Vec rv,
-                                                         const double *scal) {
+                                                         const double *scal, int first) {
   using R = typename Traits<S>::R;
   extern __shared__ __align__(16) unsigned char smem[];
   const int nthr = blockDim.x, tid = threadIdx.x, Ls = b.Ls, G = b.nrhs * Ls;
@@ -1179,7 +1190,8 @@ __global__ void __launch_bounds__(256) k_block_update_xp(const BlockArgs b, Vec 
     const double *sc = scal + ((size_t)blk * b.nrhs + r) * kScal;
     const R al = (R)sc[1], be = (R)sc[2];
     R x[24], rr[24];
-    load24<R>(reinterpret_cast<const S *>(xv.data), xv.norm, o, s, Ls, x);
+    if (first) zero24(x);  // (x_0 = 0: not read)
+    else load24<R>(reinterpret_cast<const S *>(xv.data), xv.norm, o, s, Ls, x);
     load24<R>(reinterpret_cast<const S *>(pv.data), pv.norm, o, s, Ls, p);
     load24<R>(reinterpret_cast<const S *>(rv.data), rv.norm, o, s, Ls, rr);
 #pragma unroll
@@ -1251,12 +1263,13 @@ hipError_t block_gather(int prec, const BlockArgs &b, const Vec &xs, const Vec &
   return hipGetLastError();
 }
 
-hipError_t block_scatter(int prec, const BlockArgs &b, const Vec &zglob, const Vec &xs, const Vec &rglob,
-                         const double *rr, double n_total, double *partial, hipStream_t st) {
-  if (zglob.prec != MSPCG_F64 || block_threads(b) > 256) return hipErrorInvalidValue;
+hipError_t block_scatter(int prec, const BlockArgs &b, const Vec &zglob, const Vec &xs, const Vec &ps,
+                         const double *scal, int mode, const Vec &rglob, const double *rr, double n_total,
+                         double *partial, hipStream_t st) {
+  if (zglob.prec != MSPCG_F64 || block_threads(b) > 256 || mode < 0 || mode > 2) return hipErrorInvalidValue;
   MSPCG_PREC_SWITCH(prec, hipLaunchKernelGGL(k_block_scatter<S>, dim3(block_grid(b)), dim3(block_threads(b)),
-                                             block_lds(b), st, b, (double *)zglob.data, zglob.stride, xs,
-                                             (const double *)rglob.data, rr, n_total, partial));
+                                             block_lds(b), st, b, (double *)zglob.data, zglob.stride, xs, ps, scal,
+                                             mode, (const double *)rglob.data, rr, n_total, partial));
   return hipGetLastError();
 }
 
@@ -1285,10 +1298,10 @@ hipError_t block_update_r(int prec, const BlockArgs &b, const Vec &r, const Vec 
 }
 
 hipError_t block_update_xp(int prec, const BlockArgs &b, const Vec &x, const Vec &p, const Vec &mp, const Vec &r,
-                           const double *scal, hipStream_t st) {
+                           const double *scal, int first, hipStream_t st) {
   if (block_threads(b) > 256) return hipErrorInvalidValue;
   MSPCG_PREC_SWITCH(prec, hipLaunchKernelGGL(k_block_update_xp<S>, dim3(block_grid(b)), dim3(block_threads(b)),
-                                             block_lds_mphi<S>(b), st, b, x, p, mp, r, scal));
+                                             block_lds_mphi<S>(b), st, b, x, p, mp, r, scal, first));
   return hipGetLastError();
 }
 
