@@ -381,7 +381,6 @@ int global_hop(mspcg_handle *h, int prec, int nrhs, int p, const Vec &out, const
   a.nsites = h->Vh;
   a.site_cb = h->d_order[p].as<int>();
   a.nbr = h->d_nbr[p].as<int>();
-  a.zero_site = 0;
   a.in = in.data;
   a.in_norm = in.norm;
   a.in_stride = h->Vh;
@@ -670,14 +669,13 @@ void ensure_block_vecs(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs) {
   bg->vnrhs = nrhs;
 }
 
-// Block-domain hop: the input list's zero site is its first extra site.
+// Block-domain hop arguments (lists, tables and fields of one hop of A_s).
 HopArgs block_hop_args(mspcg_handle *h, int nrhs, int nsites, const int *site_cb, const int *nbr, const Vec &in,
                        const Vec &out, int out_parity, int prec) {
   HopArgs a = base_args(h, nrhs);
   a.nsites = nsites;
   a.site_cb = site_cb;
   a.nbr = nbr;
-  a.zero_site = (int)(in.stride - kPad);
   a.in = in.data;
   a.in_norm = in.norm;
   a.in_stride = in.stride;
@@ -709,7 +707,6 @@ int block_hop(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int which, con
     a2.other_norm = in.norm;
     a2.other_stride = in.stride;
     a2.other_idx = bg->d_e2_be.as<int>();
-    a2.other_zero = bg->be_tot;
     return run_hop(h, 2, prec, 0, 0, EPI_M5_OTHER, 0, 0, a2, st);
   }
   if (which == 3) {  // f = M_5^{-+} M_phi^+ (-1/2 H^+ y) on O1
@@ -727,7 +724,6 @@ int block_hop(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int which, con
   a4.other_norm = bg->e2v.v.norm;
   a4.other_stride = bg->e2v.v.stride;
   a4.other_idx = bg->d_be_e2.as<int>();
-  a4.other_zero = bg->e2_tot;
   if (partial) {
     a4.partial = partial;
     a4.dotw = in.data;

@@ -40,7 +40,6 @@ struct HopArgs {
   const int *nbr;      // [site][8] input index of neighbour d = 2 mu + (0 fwd, 1 bwd); indexed by cb for the
                        // full lattice, by list position for block domains, where a neighbour outside the
                        // domain is stored as -1 - alt (alt: an input index whose data is loaded with weight 0)
-  int zero_site;       // input index read by inactive threads (an all-zero site of block lists)
   const void *in;
   const float *in_norm;
   long long in_stride;
@@ -52,7 +51,6 @@ struct HopArgs {
   const float *other_norm;
   long long other_stride;
   const int *other_idx;  // output list position -> index in `other`, -1 outside (zero); nullptr: identity
-  int other_zero;        // zero site of `other` (inactive threads)
   double scale;
   const void *mat;     // EPI_M5INV: chain coefficients of X (kChainHead + Ls values in the compute type)
   double mphi_b, mphi_c, mf, m5_alpha, m5_beta;

@@ -70,6 +70,11 @@ __device__ inline double perm(int addr, double x) {
 // fills whole waves; otherwise (Ls = 24; Ls = 12 with 8 right-hand sides) the
 // groups are packed densely and exchange through LDS with barriers.
 constexpr int kXDpp16 = 0, kXPerm = 1, kXLds = 2;
+// Exchanges through LDS (and the M_5^{-1} transposition) give every thread a
+// row of kRow values: the offsets inside a row are instruction immediates, and
+// with an odd row length the rows of consecutive threads start on distinct
+// banks.
+constexpr int kRow = 25;
 static inline int xmode(int Ls, int nrhs) {
   if (Ls == 16) return kXDpp16;
   if (Ls > 64) return kXLds;
@@ -117,16 +122,16 @@ __device__ inline void pchi_comb(R *lds, int nthr, int tid, int s, int Ls, R a, 
   } else {
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 24; ++k) lds[k * nthr + tid] = v[k];
+    for (int k = 0; k < 24; ++k) lds[tid * kRow + k] = v[k];
     __syncthreads();
     const int tm = (s > 0) ? tid - 1 : tid + Ls - 1;
     const int tp = (s < Ls - 1) ? tid + 1 : tid - (Ls - 1);
     const int tu = DAG ? tp : tm;
     const int tl = DAG ? tm : tp;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) v[k] = a * v[k] + cu * lds[k * nthr + tu];
+    for (int k = 0; k < 12; ++k) v[k] = a * v[k] + cu * lds[tu * kRow + k];
 #pragma unroll
-    for (int k = 12; k < 24; ++k) v[k] = a * v[k] + cl * lds[k * nthr + tl];
+    for (int k = 12; k < 24; ++k) v[k] = a * v[k] + cl * lds[tl * kRow + k];
   }
 }
 
@@ -157,16 +162,16 @@ __device__ inline void pchi_add(R *lds, int nthr, int tid, int s, int Ls, R mf, 
   } else {
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 24; ++k) lds[k * nthr + tid] = B[k];
+    for (int k = 0; k < 24; ++k) lds[tid * kRow + k] = B[k];
     __syncthreads();
     const int tm = (s > 0) ? tid - 1 : tid + Ls - 1;
     const int tp = (s < Ls - 1) ? tid + 1 : tid - (Ls - 1);
     const int tu = DAG ? tp : tm;
     const int tl = DAG ? tm : tp;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) A[k] += cu * lds[k * nthr + tu];
+    for (int k = 0; k < 12; ++k) A[k] += cu * lds[tu * kRow + k];
 #pragma unroll
-    for (int k = 12; k < 24; ++k) A[k] += cl * lds[k * nthr + tl];
+    for (int k = 12; k < 24; ++k) A[k] += cl * lds[tl * kRow + k];
   }
 }
 
@@ -198,14 +203,14 @@ __device__ inline void project_pre(R *lds, int nthr, int tid, int s, int Ls, R c
   } else {
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 24; ++k) lds[k * nthr + tid] = v[k];
+    for (int k = 0; k < 24; ++k) lds[tid * kRow + k] = v[k];
     __syncthreads();
     const int tm = (s > 0) ? tid - 1 : tid + Ls - 1;
     const int tp = (s < Ls - 1) ? tid + 1 : tid - (Ls - 1);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      w[k] = lds[k * nthr + tm];
-      w[12 + k] = lds[(12 + k) * nthr + tp];
+      w[k] = lds[tm * kRow + k];
+      w[12 + k] = lds[tp * kRow + 12 + k];
     }
   }
   R X[12], Y[12], Xw[12], Yw[12];
@@ -259,18 +264,18 @@ __device__ inline void exchange_pre_raw(float *lds, int nthr, int tid, int s, in
     uint32_t *lw = reinterpret_cast<uint32_t *>(lds);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 12; ++i) lw[i * nthr + tid] = raw.word(i);
-    lds[12 * nthr + tid] = raw.n;
+    for (int i = 0; i < 12; ++i) lw[tid * kRow + i] = raw.word(i);
+    lds[tid * kRow + 12] = raw.n;
     __syncthreads();
     const int tm = (s > 0) ? tid - 1 : tid + Ls - 1;
     const int tp = (s < Ls - 1) ? tid + 1 : tid - (Ls - 1);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      w.set_word(i, lw[i * nthr + tm]);
-      w.set_word(6 + i, lw[(6 + i) * nthr + tp]);
+      w.set_word(i, lw[tm * kRow + i]);
+      w.set_word(6 + i, lw[tp * kRow + 6 + i]);
     }
-    nm = lds[12 * nthr + tm];
-    np = lds[12 * nthr + tp];
+    nm = lds[tm * kRow + 12];
+    np = lds[tp * kRow + 12];
   }
 }
 
@@ -372,12 +377,11 @@ __device__ inline void hop_dir_h16(float *lds, int nthr, int tid, int s, int Ls,
 //
 // The Ls values of one (site, rhs) sit on the Ls consecutive threads of its
 // group; they are transposed through LDS (rows = positions i, one row of
-// kChainStride words per thread: an odd stride, so a row store of all lanes
+// kRow words per thread: an odd stride, so a row store of all lanes
 // and a column load of all lanes both spread over the banks), lane t of the
 // group runs the recurrence of columns t, t + Ls, ... < 24, and the rows are
 // read back.  A chirality whose shift takes s+1 is stored with its rows
 // reversed, so every column runs toward increasing i.
-constexpr int kChainStride = 25;
 
 template <typename R, int LSC>
 __device__ inline void chain_columns(R *Tg, int t, int Ls_rt, const R *cf, R sig) {
@@ -388,7 +392,7 @@ __device__ inline void chain_columns(R *Tg, int t, int Ls_rt, const R *cf, R sig
     if constexpr (LSC > 0) {  // the column in registers
       R x[LSC];
 #pragma unroll
-      for (int i = 0; i < LSC; ++i) x[i] = c[i * kChainStride];
+      for (int i = 0; i < LSC; ++i) x[i] = c[i * kRow];
       R prev = x[0];
       x[0] = fma(wrap, x[LSC - 1], x[0]);
 #pragma unroll
@@ -399,30 +403,30 @@ __device__ inline void chain_columns(R *Tg, int t, int Ls_rt, const R *cf, R sig
       }
       const R zl = x[LSC - 1];
 #pragma unroll
-      for (int i = 0; i < LSC; ++i) c[i * kChainStride] = sig * fma(cf[4 + i], zl, x[i]);
+      for (int i = 0; i < LSC; ++i) c[i * kRow] = sig * fma(cf[4 + i], zl, x[i]);
     } else {  // any Ls: in place in LDS
       R prev = c[0];
-      R z = fma(wrap, c[(Ls - 1) * kChainStride], prev);
+      R z = fma(wrap, c[(Ls - 1) * kRow], prev);
       c[0] = z;
       for (int i = 1; i < Ls; ++i) {
-        const R cur = c[i * kChainStride];
+        const R cur = c[i * kRow];
         z = fma(q, z, fma(rho, prev, cur));
-        c[i * kChainStride] = z;
+        c[i * kRow] = z;
         prev = cur;
       }
-      for (int i = 0; i < Ls; ++i) c[i * kChainStride] = sig * fma(cf[4 + i], z, c[i * kChainStride]);
+      for (int i = 0; i < Ls; ++i) c[i * kRow] = sig * fma(cf[4 + i], z, c[i * kRow]);
     }
   }
 }
 
-// lds: kChainStride * nthr values; G: groups per wave of the lane layout (0:
+// lds: kRow * nthr values; G: groups per wave of the lane layout (0:
 // dense packing, groups may straddle waves: workgroup barriers; otherwise the
 // groups of a wave only touch that wave's rows).  Must be reached by all
 // threads of the workgroup.
 template <int TR, typename R, int LSC>
 __device__ inline void m5_chain_t(R *lds, int tid, int s, int Ls_rt, int G, const R *cf, R scale, R v[24]) {
   const int Ls = LSC > 0 ? LSC : Ls_rt;
-  R *Tg = lds + (size_t)(tid - s) * kChainStride;  // this group's rows
+  R *Tg = lds + (size_t)(tid - s) * kRow;  // this group's rows
   const int rp = TR ? Ls - 1 - s : s;              // row of chirality + (reals 0..11)
   const int rm = TR ? s : Ls - 1 - s;              // row of chirality -
   // The idle lanes past a wave's last whole group (whole-wave layouts) form
@@ -431,18 +435,18 @@ __device__ inline void m5_chain_t(R *lds, int tid, int s, int Ls_rt, int G, cons
   if (G == 0) __syncthreads();                     // (earlier exchanges through the same words)
   if (own) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) Tg[rp * kChainStride + k] = v[k];
+    for (int k = 0; k < 12; ++k) Tg[rp * kRow + k] = v[k];
 #pragma unroll
-    for (int k = 12; k < 24; ++k) Tg[rm * kChainStride + k] = v[k];
+    for (int k = 12; k < 24; ++k) Tg[rm * kRow + k] = v[k];
   }
   if (G == 0) __syncthreads(); else wave_lds_sync();
   if (own) chain_columns<R, LSC>(Tg, s, Ls, cf, cf[3] * scale);
   if (G == 0) __syncthreads(); else wave_lds_sync();
   if (own) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) v[k] = Tg[rp * kChainStride + k];
+    for (int k = 0; k < 12; ++k) v[k] = Tg[rp * kRow + k];
 #pragma unroll
-    for (int k = 12; k < 24; ++k) v[k] = Tg[rm * kChainStride + k];
+    for (int k = 12; k < 24; ++k) v[k] = Tg[rm * kRow + k];
   }
 }
 
@@ -496,12 +500,12 @@ __device__ inline void wg_partial(double *ldsd, int nthr, int tid, int Ls, int n
 // GLOBAL: the output list is the whole parity (site_cb a permutation of cb in
 // column-sweep order); neighbour tables, outputs and the `other`/dot operands are
 // indexed by cb.  Otherwise (block domains) they are indexed by the position
-// in the list, and neighbours outside the domain point at the input list's
-// zero site, which is never written.
+// in the list, and neighbours outside the domain enter with weight zero.
 // Occupancy the register allocation of the hop kernel is held to (waves per SIMD).
 // (the LDS exchange keeps more values live; FP64 doubles every register)
 template <typename S, int XM> struct HopWaves { static constexpr int value = XM == kXLds ? 3 : 4; };
 template <int XM> struct HopWaves<double, XM> { static constexpr int value = 2; };
+template <int XM> struct HopWaves<float, XM> { static constexpr int value = 3; };  // (FP32 spinors: 4 would spill)
 
 template <typename S, int DAG, int PRE, int EPI, int DOT, int GLOBAL, int XM>
 __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(const HopArgs a) {
@@ -527,7 +531,7 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
     sl = g / nrhs;
   }
   R *Lk = reinterpret_cast<R *>(smem);  // [nsite_wg][8][18] links of this workgroup's sites
-  R *lds = Lk + nsw * 144;              // exchanges: [24][nthr] (LDS mode), [nthr][kChainStride] (M_5^{-1})
+  R *lds = Lk + nsw * 144;              // exchange rows [nthr][kRow] (LDS mode, M_5^{-1})
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int site = tile * nsw + sl;
   const int cbr = (site < a.nsites) ? a.site_cb[site] : -1;
@@ -538,8 +542,10 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
   // The eight neighbour indices are loaded once, with two 16-byte loads, and
   // kept in registers (rotated by two per direction pair below): no spinor
   // load ever waits for an index load issued after an earlier spinor load.
-  // Block domains: bit d of outm marks a neighbour outside the domain, whose
-  // (substitute) data enters with weight zero.
+  // Block domains: a neighbour outside the domain is stored as -1 - n with n
+  // an in-domain substitute whose data enters with weight zero (bit d of
+  // outm).  Inactive lanes take the neighbours of row 0: they compute on valid
+  // data and store nothing.
   int nbw[8];
   int outm = 0;
   {
@@ -549,11 +555,10 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
 #pragma unroll
     for (int d = 0; d < 8; ++d) {
       if (GLOBAL) {
-        nbw[d] = active ? qa[d] : a.zero_site;
-      } else {  // (inactive lanes read zero sites, spread over the kPad of them)
-        const bool out = qa[d] < 0;
-        nbw[d] = active ? (out ? -1 - qa[d] : qa[d]) : a.zero_site + ((site * 8 + d) & 63);
-        outm |= (active && out) ? (1 << d) : 0;
+        nbw[d] = qa[d];
+      } else {
+        nbw[d] = qa[d] ^ (qa[d] >> 31);  // (-1 - n = ~n)
+        outm |= (int)((uint32_t)qa[d] >> 31) << d;
       }
     }
   }
@@ -709,8 +714,7 @@ template <typename S>
 static size_t hop_lds_bytes(const HopArgs &a, int nthr, int epi, int dot, int xm) {
   using R = typename Traits<S>::R;
   size_t b = (size_t)144 * a.nsite_wg * sizeof(R);
-  if (epi == EPI_M5INV) b += (size_t)kChainStride * nthr * sizeof(R);
-  else if (xm == kXLds) b += (size_t)24 * nthr * sizeof(R);
+  if (epi == EPI_M5INV || xm == kXLds) b += (size_t)kRow * nthr * sizeof(R);
   if (dot) b = std::max(b, (size_t)2 * nthr * sizeof(double));
   return b;
 }
@@ -823,7 +827,7 @@ hipError_t launch_op5(int prec, const Op5Args &a, hipStream_t st) {
   const int grid = (a.nsites + a.nsite_wg - 1) / a.nsite_wg;
   if (a.nsite_wg < 1 || nthr > 256 || grid < 1) return hipErrorInvalidValue;
   const size_t rsz = (prec == MSPCG_F64) ? 8 : 4;
-  const size_t lds = (size_t)kChainStride * nthr * rsz;
+  const size_t lds = (size_t)kRow * nthr * rsz;
   const dim3 blk = (xm == kXLds) ? dim3(a.Ls, a.nrhs, a.nsite_wg) : dim3(nthr);
   switch (prec) {
     case MSPCG_F64: launch_op5_t<double>(a, dim3(grid), blk, lds, st); break;
@@ -1242,7 +1246,7 @@ static inline size_t block_lds(const BlockArgs &b) { return (size_t)2 * block_th
 // the kernels that form M_phi p exchange 24 reals per thread through LDS
 template <typename S>
 static inline size_t block_lds_mphi(const BlockArgs &b) {
-  return std::max(block_lds(b), (size_t)24 * block_threads(b) * sizeof(typename Traits<S>::R));
+  return std::max(block_lds(b), (size_t)kRow * block_threads(b) * sizeof(typename Traits<S>::R));
 }
 
 #define MSPCG_PREC_SWITCH(prec, CALL)                 \
