@@ -758,9 +758,16 @@ BlockArgs block_args(mspcg_handle *h, BlockGeom *bg, int nrhs) {
   return ba;
 }
 
+// What the block state holds after run_block_cg, for the kernels that form z
+// from it: 0 = the final iterate in x; 1 = x and the last step alpha p (fixed
+// k > 1); 2 = only the step (k = 1).
+int scatter_mode(int k, double inner_tol) { return (inner_tol > 0.0 || k < 1) ? 0 : (k == 1 ? 2 : 1); }
+
 // The preconditioner: z = sum_s P_s CG_k(A_s, P_s r) for every (block, rhs).
-// r, z: FP64 even fields.  rr: device |r|^2 per rhs (RMS scaling); partial_zr
-// (optional): workgroup partials of Re<z, r> for the outer solver.
+// r, z: FP64 even fields (z without data: only the partials are formed, and
+// block_scatter_xpay takes z from the block state).  rr: device |r|^2 per rhs
+// (RMS scaling); partial_zr (optional): workgroup partials of Re<z, r> for the
+// outer solver.
 void run_block_cg(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int k, double inner_tol, const Vec &z,
                   const Vec &r, const double *rr, double *partial_zr, int *nparts_zr, hipStream_t st) {
   ensure_links(h, prec, st);
@@ -777,7 +784,8 @@ void run_block_cg(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int k, dou
   // and the last iteration's x update happens in the scatter (x + alpha p,
   // with no r update: nothing reads r after it).  Precision-based stopping
   // keeps every step, since its test reads |r|^2 after the last update.
-  const bool lazy_x = !stop && k >= 1;
+  const int smode = scatter_mode(k, inner_tol);
+  const bool lazy_x = smode != 0;
   HIPCHK(block_gather(prec, ba, lazy_x ? Vec() : bg->x.v, bg->r.v, bg->p.v, bg->mp.v, r, rr, n_total, part, st));
   HIPCHK(block_scalars(2, ba, part, scal, st));
   if (stop) HIPCHK(inner_stop(0, bg->nb, nrhs, inner_tol, scal, stopd, st));
@@ -796,7 +804,6 @@ void run_block_cg(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int k, dou
       HIPCHK(block_update_xr(prec, ba, bg->x.v, bg->r.v, bg->p.v, bg->Ap.v, scal, part, st));
     }
   }
-  const int smode = !lazy_x ? 0 : (k == 1 ? 2 : 1);
   HIPCHK(block_scatter(prec, ba, z, bg->x.v, bg->p.v, scal, smode, r, rr, n_total, partial_zr ? partial_zr : part,
                        st));
   if (nparts_zr) *nparts_zr = (ba.nsites + ba.nsite_wg - 1) / ba.nsite_wg;
@@ -993,13 +1000,29 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
       HIPCHK(e);
       h->graphs[key] = exec;
     };
+    // One sweep with the Fletcher-Reeves beta: z is never stored; the direction
+    // update p = z + beta p reads it from the block state (block_scatter_xpay)
+    const bool fuse_p = pc && !s->flexible_beta && pc->n_sweeps <= 1;
+    auto update_p = [&](bool first) {  // p = z (first) or z + beta p
+      if (fuse_p) {
+        tm.mark(PhaseTimer::PRECOND);
+        HIPCHK(block_scatter_xpay(pc->inner_prec, block_args(h, bg, nrhs), P, bg->x.v, bg->p.v,
+                                  bg->scal.as<double>(), scatter_mode(pc->n_inner, pc->inner_tol), w.rr,
+                                  (double)h->Vh * Ls * 24, w.beta, first ? 1 : 0, st));
+        tm.mark(PhaseTimer::BLAS);
+      } else if (first) {
+        HIPCHK(blas_axpby(pd, 1.0, zd, 0.0, zd, n, nrhs, st));
+      } else {
+        HIPCHK(blas_xpay(pd, zd, w.beta, n, nrhs, st));
+      }
+    };
     auto precond = [&] {  // z = M^{-1} r and rho_new = <z, r> into w.tmp
       if (!pc) {
         HIPCHK(hipMemcpyAsync(w.tmp, w.rr, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
         return;
       }
       tm.mark(PhaseTimer::PRECOND);
-      precond_one(Z, R, w.rr, w.tmp);
+      precond_one(fuse_p ? Vec() : Z, R, w.rr, w.tmp);
       if (pc->n_sweeps > 1) {
         more_sweeps(h, nrhs, pc->n_sweeps, Z, R, w.rrt, part, st,
                     [&](const Vec &z2, const Vec &t, double *rrt) { precond_one(z2, t, rrt, w.zrt); });
@@ -1027,7 +1050,7 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
     if (any) {
       precond();
       if (pc) inner += (long long)pc->n_inner * std::max(1, pc->n_sweeps);
-      HIPCHK(blas_axpby(pd, 1.0, zd, 0.0, zd, n, nrhs, st));  // p = z
+      update_p(true);  // p = z
       HIPCHK(hipMemcpyAsync(w.rho, w.tmp, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
       while (it < s->max_iter) {
         tm.mark(PhaseTimer::OP);
@@ -1070,7 +1093,7 @@ mspcg_status solve(mspcg_handle *h, mspcg_field *x, const mspcg_field *b, const 
         } else {
           HIPCHK(solver_scalars(1, nrhs, w.active, w.rho, w.tmp, w.beta, st));
         }
-        HIPCHK(blas_xpay(pd, zd, w.beta, n, nrhs, st));
+        update_p(false);
       }
     }
     // final true residual

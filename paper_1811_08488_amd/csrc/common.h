@@ -134,7 +134,9 @@ __device__ inline float site_scale(const R v[24], float &inv) {
   float m = 0.f;
 #pragma unroll
   for (int k = 0; k < 24; ++k) m = fmaxf(m, fabsf((float)v[k]));
-  inv = m > 0.f ? 1.f / m : 0.f;
+  // (the hardware reciprocal: within one FP32 ulp, far below the 2^-11 or
+  // 2^-9 to which the scaled values are then rounded)
+  inv = m > 0.f ? __builtin_amdgcn_rcpf(m) : 0.f;
   return m;
 }
 template <typename R>

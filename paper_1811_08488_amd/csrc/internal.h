@@ -128,10 +128,16 @@ hipError_t block_gather(int prec, const BlockArgs &b, const Vec &xs, const Vec &
                         const Vec &rglob, const double *rr, double n_total, double *partial, hipStream_t st);
 // z(cb) = v / scale with v = x_s (mode 0), x_s + alpha p_s (mode 1: the last
 // inner iteration's x update) or alpha p_s (mode 2: a single inner iteration);
-// partial Re<z, r> per workgroup (FP64 r, z)
+// partial Re<z, r> per workgroup (FP64 r, z; no z data: only the partials)
 hipError_t block_scatter(int prec, const BlockArgs &b, const Vec &zglob, const Vec &xs, const Vec &ps,
                          const double *scal, int mode, const Vec &rglob, const double *rr, double n_total,
                          double *partial, hipStream_t st);
+// p(cb) = v / scale + beta[rhs] p(cb) (first: p = v / scale), v as in
+// block_scatter: the outer direction update with the preconditioned residual
+// taken straight from the blocks (FP64 p)
+hipError_t block_scatter_xpay(int prec, const BlockArgs &b, const Vec &pglob, const Vec &xs, const Vec &ps,
+                              const double *scal, int mode, const double *rr, double n_total, const double *beta,
+                              int first, hipStream_t st);
 // per (block, rhs): mode 0: alpha = rho/sum(partials) (0 if degenerate)
 //                   mode 1: rho_new = sum; beta = rho_new/rho (0 if rho = 0); rho = rho_new
 //                   mode 2: rho = sum (initialisation)

@@ -1075,7 +1075,8 @@ __global__ void __launch_bounds__(256) k_block_gather(const BlockArgs b, Vec xs,
 template <typename S>
 __global__ void __launch_bounds__(256) k_block_scatter(const BlockArgs b, double *zg, long long zg_stride, Vec xs,
                                                         Vec ps, const double *scal, int mode, const double *rg,
-                                                        const double *rr, double n_total, double *partial) {
+                                                        long long rg_stride, const double *rr, double n_total,
+                                                        double *partial) {
   using R = typename Traits<S>::R;
   extern __shared__ __align__(16) unsigned char smem[];
   const int nthr = blockDim.x, tid = threadIdx.x, Ls = b.Ls, G = b.nrhs * Ls;
@@ -1099,15 +1100,52 @@ __global__ void __launch_bounds__(256) k_block_scatter(const BlockArgs b, double
     double z[24], t[24];
 #pragma unroll
     for (int k = 0; k < 24; ++k) z[k] = inv * (double)v[k];
-    const size_t g = (size_t)r * zg_stride + cb;
-    store24<double>(zg, nullptr, g, s, Ls, z);
+    if (zg) store24<double>(zg, nullptr, (size_t)r * zg_stride + cb, s, Ls, z);  // (none: only the partials)
     if (rg) {
-      load24<double>(rg, nullptr, g, s, Ls, t);
+      load24<double>(rg, nullptr, (size_t)r * rg_stride + cb, s, Ls, t);
 #pragma unroll
       for (int k = 0; k < 24; ++k) val += z[k] * t[k];
     }
   }
   wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, b.nrhs, b.nsite_wg, 0, val, partial, blockIdx.x);
+}
+
+// The outer direction update fused with the scatter: p(cb) = v / scale +
+// beta p(cb) (first: p = v / scale) with v as in k_block_scatter, so the
+// preconditioned residual z is never stored.
+template <typename S>
+__global__ void __launch_bounds__(256) k_block_scatter_xpay(const BlockArgs b, double *pg, long long pg_stride, Vec xs,
+                                                             Vec ps, const double *scal, int mode, const double *rr,
+                                                             double n_total, const double *beta, int first) {
+  using R = typename Traits<S>::R;
+  const int tid = threadIdx.x, Ls = b.Ls, G = b.nrhs * Ls;
+  const int sl = tid / G, rem = tid - sl * G, r = rem / Ls, s = rem - r * Ls;
+  const int site = blockIdx.x * b.nsite_wg + sl;
+  const int cb = site < b.nsites ? b.be_cb[site] : -1;
+  if (cb < 0) return;
+  const double inv = rr ? (rr[r] > 0 ? sqrt(rr[r] / n_total) : 0.0) : 1.0;
+  const size_t o = (size_t)r * xs.stride + site;
+  R v[24];
+  if (mode == 2) zero24(v); else load24<R>(reinterpret_cast<const S *>(xs.data), xs.norm, o, s, Ls, v);
+  if (mode != 0) {
+    const R al = (R)scal[((size_t)b.be_blk[site] * b.nrhs + r) * kScal + 1];
+    R pv[24];
+    load24<R>(reinterpret_cast<const S *>(ps.data), ps.norm, o, s, Ls, pv);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) v[k] = fma(al, pv[k], v[k]);
+  }
+  const size_t g = (size_t)r * pg_stride + cb;
+  double pn[24];
+  if (first) {
+#pragma unroll
+    for (int k = 0; k < 24; ++k) pn[k] = inv * (double)v[k];
+  } else {
+    load24<double>(pg, nullptr, g, s, Ls, pn);
+    const double be = beta[r];
+#pragma unroll
+    for (int k = 0; k < 24; ++k) pn[k] = fma(be, pn[k], inv * (double)v[k]);
+  }
+  store24<double>(pg, nullptr, g, s, Ls, pn);
 }
 
 template <typename S>
@@ -1273,7 +1311,17 @@ hipError_t block_scatter(int prec, const BlockArgs &b, const Vec &zglob, const V
   if (zglob.prec != MSPCG_F64 || block_threads(b) > 256 || mode < 0 || mode > 2) return hipErrorInvalidValue;
   MSPCG_PREC_SWITCH(prec, hipLaunchKernelGGL(k_block_scatter<S>, dim3(block_grid(b)), dim3(block_threads(b)),
                                              block_lds(b), st, b, (double *)zglob.data, zglob.stride, xs, ps, scal,
-                                             mode, (const double *)rglob.data, rr, n_total, partial));
+                                             mode, (const double *)rglob.data, rglob.stride, rr, n_total, partial));
+  return hipGetLastError();
+}
+
+hipError_t block_scatter_xpay(int prec, const BlockArgs &b, const Vec &pglob, const Vec &xs, const Vec &ps,
+                              const double *scal, int mode, const double *rr, double n_total, const double *beta,
+                              int first, hipStream_t st) {
+  if (pglob.prec != MSPCG_F64 || block_threads(b) > 256 || mode < 0 || mode > 2) return hipErrorInvalidValue;
+  MSPCG_PREC_SWITCH(prec, hipLaunchKernelGGL(k_block_scatter_xpay<S>, dim3(block_grid(b)), dim3(block_threads(b)), 0,
+                                             st, b, (double *)pglob.data, pglob.stride, xs, ps, scal, mode, rr,
+                                             n_total, beta, first));
   return hipGetLastError();
 }
 
