@@ -217,10 +217,12 @@ mspcg_status mspcg_debug_block_sites(mspcg_handle *h, const int nblk[4], int blo
  * (Sec. 2.3) for every block at once, `reps` times on `stream`, exactly as an
  * inner CG iteration of local_block_cg launches it (same kernel, domain lists
  * and tuned shape; storage pc->inner_prec, nrhs right-hand sides):
- *   hop 1: B_e -> O1, M_phi on the input, dense M_phi M_5^{-1} epilogue
- *   hop 2: O1 -> E2, plus M_5 applied to the block vector
- *   hop 3: E2 -> O1, daggered, dense M_5^{-+} M_phi^+ epilogue
- *   hop 4: O1 -> B_e, daggered, plus M_5^+ y, with the per-block <p, A_s p> partials
+ *   hop 1: B_e -> O1, input M_phi p (stored beside p), M_phi M_5^{-1} epilogue
+ *   hop 2: O1 -> E2, plus M_5 applied to the block vector; with the snake
+ *          terms also the per-block <p, A_s p> = |D_PC P_s p|^2 partials
+ *   hop 3: E2 -> O1, daggered, M_5^{-+} M_phi^+ epilogue
+ *   hop 4: O1 -> B_e, daggered, plus M_5^+ y; without the snake terms
+ *          (pc->no_snake) it forms the <p, A_s p> partials instead
  * on the handle's block work vectors as the last preconditioner call left
  * them (zeros before any).  sites (may be NULL) receives the 4D sites of the
  * launch's input and output domains, summed over blocks (padding excluded):

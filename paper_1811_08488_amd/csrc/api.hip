@@ -119,7 +119,8 @@ struct BlockGeom {
   std::vector<int> be_off, o1_off, e2_off;   // padded offsets, size nb+1
   std::vector<int> be_n, o1_n, e2_n;         // true counts
   std::vector<int> be_lex, o1_lex, e2_lex;   // lex per padded entry (-1 padding)
-  DBuf d_be_cb, d_be_blk, d_be_nbr, d_be_e2, d_o1_cb, d_o1_nbr_be, d_o1_nbr_e2, d_e2_cb, d_e2_nbr, d_e2_be, d_be_off;
+  DBuf d_be_cb, d_be_blk, d_be_nbr, d_be_e2, d_o1_cb, d_o1_nbr_be, d_o1_nbr_e2, d_e2_cb, d_e2_nbr, d_e2_be, d_be_off,
+      d_e2_off;
   // work vectors (inner precision); `gen` changes whenever they are reallocated
   // or cleared for another layout, so that graphs captured on them are never replayed
   int vprec = -1, vnrhs = 0;
@@ -608,6 +609,7 @@ BlockGeom *get_blocks(mspcg_handle *h, const int nblk[4], int no_snake, hipStrea
   upload(bg->d_e2_nbr, e2_nbr, st);
   upload(bg->d_e2_be, e2_be, st);
   upload(bg->d_be_off, bg->be_off, st);
+  upload(bg->d_e2_off, bg->e2_off, st);
   HIPCHK(hipStreamSynchronize(st));
   BlockGeom *raw = bg.get();
   h->blocks[key] = std::move(bg);
@@ -643,7 +645,9 @@ void ensure_block_vecs(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs) {
   bg->Ap.ensure(prec, nrhs, bg->be_tot + kPad, Ls);
   bg->o1v.ensure(prec, nrhs, bg->o1_tot + kPad, Ls);
   bg->e2v.ensure(prec, nrhs, bg->e2_tot + kPad, Ls);
-  const int nwg = bg->be_tot;  // upper bound on workgroups (nsite_wg >= 1)
+  // upper bound on the workgroups of a hop with fused partials (nsite_wg >= 1;
+  // the tuner tries 1): the second hop runs on E2, the last on B_e
+  const int nwg = std::max(bg->be_tot, bg->e2_tot);
   bg->partial.ensure((size_t)nwg * nrhs * sizeof(double));
   bg->scal.ensure((size_t)bg->nb * nrhs * kScal * sizeof(double));
   bg->rrbuf.ensure((size_t)nrhs * sizeof(double) + 16);
@@ -707,7 +711,10 @@ int block_hop(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int which, con
     a2.other_norm = in.norm;
     a2.other_stride = in.stride;
     a2.other_idx = bg->d_e2_be.as<int>();
-    return run_hop(h, 2, prec, 0, 0, EPI_M5_OTHER, 0, 0, a2, st);
+    // (with partial: |y|^2 per workgroup; y = D_PC P_s in on all of E2, so the
+    // sum over a block is <in, A_s in>)
+    a2.partial = partial;
+    return run_hop(h, 2, prec, 0, 0, EPI_M5_OTHER, partial ? 1 : 0, 0, a2, st);
   }
   if (which == 3) {  // f = M_5^{-+} M_phi^+ (-1/2 H^+ y) on O1
     HopArgs a3 = block_hop_args(h, nrhs, bg->o1_tot, bg->d_o1_cb.as<int>(), bg->d_o1_nbr_e2.as<int>(), bg->e2v.v,
@@ -734,12 +741,22 @@ int block_hop(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int which, con
 }
 
 // out = A_s in for every block at once on the halo-extended domains
-// (B_e -> O1 -> E2 -> O1 -> B_e); optional partial Re<in, out> per workgroup.
+// (B_e -> O1 -> E2 -> O1 -> B_e); optional partial sums of Re<in, out> per
+// workgroup.  With the snake terms A_s = P_s D_PC^+ D_PC P_s, so
+// <in, A_s in> = |D_PC P_s in|^2 is summed by the second hop over E2 (the
+// whole support of D_PC P_s in) from values it already holds, and the last
+// hop does not read `in` again; the truncated operator sums Re<in, out> in the
+// last hop.  Returns the sites per workgroup of the hop that formed the
+// partials and sets *off to that hop's per-block offsets in its list.
 int block_hops(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, const Vec &in, const Vec &in_mp, const Vec &out,
-               double *partial, hipStream_t st) {
-  for (int which = 1; which <= 3; ++which) block_hop(h, bg, prec, nrhs, which, in, in_mp, out, nullptr, st);
-  const int grid = block_hop(h, bg, prec, nrhs, 4, in, in_mp, out, partial, st);
-  return (bg->be_tot + grid - 1) / grid;  // sites per workgroup of the last hop
+               double *partial, hipStream_t st, const int **off = nullptr) {
+  const bool on_e2 = partial && !bg->no_snake;
+  block_hop(h, bg, prec, nrhs, 1, in, in_mp, out, nullptr, st);
+  const int grid2 = block_hop(h, bg, prec, nrhs, 2, in, in_mp, out, on_e2 ? partial : nullptr, st);
+  block_hop(h, bg, prec, nrhs, 3, in, in_mp, out, nullptr, st);
+  const int grid4 = block_hop(h, bg, prec, nrhs, 4, in, in_mp, out, on_e2 ? nullptr : partial, st);
+  if (off) *off = on_e2 ? bg->d_e2_off.as<int>() : bg->d_be_off.as<int>();
+  return on_e2 ? (bg->e2_tot + grid2 - 1) / grid2 : (bg->be_tot + grid4 - 1) / grid4;
 }
 
 BlockArgs block_args(mspcg_handle *h, BlockGeom *bg, int nrhs) {
@@ -791,7 +808,7 @@ void run_block_cg(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int k, dou
   if (stop) HIPCHK(inner_stop(0, bg->nb, nrhs, inner_tol, scal, stopd, st));
   for (int it = 0; it < k; ++it) {
     BlockArgs ba4 = ba;
-    ba4.nsite_wg = block_hops(h, bg, prec, nrhs, bg->p.v, bg->mp.v, bg->Ap.v, part, st);
+    ba4.nsite_wg = block_hops(h, bg, prec, nrhs, bg->p.v, bg->mp.v, bg->Ap.v, part, st, &ba4.be_off);
     HIPCHK(block_scalars(0, ba4, part, scal, st));
     if (stop) HIPCHK(inner_stop(1, bg->nb, nrhs, inner_tol, scal, stopd, st));
     if (it + 1 < k) {
@@ -1540,8 +1557,11 @@ mspcg_status mspcg_debug_block_hop(mspcg_handle *h, const mspcg_precond *pc, int
     ensure_links(h, prec, st);
     ensure_block_vecs(h, bg, prec, nrhs);
     double *part = bg->partial.as<double>();
+    // (the fused dot product where the solve has it: the second hop with the
+    // snake terms, the last without)
+    const int dot_hop = bg->no_snake ? 4 : 2;
     for (int i = 0; i < reps; ++i)
-      block_hop(h, bg, prec, nrhs, hop, bg->p.v, bg->mp.v, bg->Ap.v, hop == 4 ? part : nullptr, st);
+      block_hop(h, bg, prec, nrhs, hop, bg->p.v, bg->mp.v, bg->Ap.v, hop == dot_hop ? part : nullptr, st);
     if (sites) {
       // input and output domains: 1: B_e -> O1, 2: O1 -> E2, 3: E2 -> O1, 4: O1 -> B_e
       long long nbe = 0, no1 = 0, ne2 = 0;

@@ -54,7 +54,7 @@ struct HopArgs {
   double scale;
   const void *mat;     // EPI_M5INV: chain coefficients of X (kChainHead + Ls values in the compute type)
   double mphi_b, mphi_c, mf, m5_alpha, m5_beta;
-  double *partial;     // DOT: [gridDim.x][nrhs] partial sums of Re<w, out>
+  double *partial;     // DOT: [gridDim.x][nrhs] partial sums of Re<w, out> (no w: |out|^2)
   const void *dotw;
   const float *dotw_norm;
   long long dotw_stride;

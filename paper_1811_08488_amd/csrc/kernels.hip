@@ -696,14 +696,15 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
 
   if (active) store24<R>(reinterpret_cast<S *>(a.out), a.out_norm, (size_t)r * a.out_stride + self, s, Ls, acc);
 
-  if (DOT) {
+  if (DOT) {  // Re<w, out>, or |out|^2 without w
     double val = 0;
     if (active) {
       R w[24];
-      load24<R>(reinterpret_cast<const S *>(a.dotw), a.dotw_norm, (size_t)r * a.dotw_stride + self, s, Ls, w);
+      if (a.dotw)
+        load24<R>(reinterpret_cast<const S *>(a.dotw), a.dotw_norm, (size_t)r * a.dotw_stride + self, s, Ls, w);
       R t = 0;
 #pragma unroll
-      for (int k = 0; k < 24; ++k) t += w[k] * acc[k];
+      for (int k = 0; k < 24; ++k) t += (a.dotw ? w[k] : acc[k]) * acc[k];
       val = (double)t;
     }
     wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, nrhs, nsw, G, val, a.partial, tile);
@@ -755,6 +756,7 @@ static hipError_t dispatch_hop(int dagger, int pre, int epi, int dot, int global
                                             // neighbours outside a domain enter with weight zero, which needs
                                             // the input unmixed: no M_phi on the input there)
   MSPCG_HOP(0, 0, EPI_M5_OTHER, 0, 0)
+  MSPCG_HOP(0, 0, EPI_M5_OTHER, 1, 0)          //   ... with the fused |out|^2 (<p, A_s p> = |D_PC P_s p|^2)
   MSPCG_HOP(1, 0, EPI_M5INV, 0, 0)
   MSPCG_HOP(1, 0, EPI_M5DAG_MPHIDAG, 0, 0)
   MSPCG_HOP(1, 0, EPI_M5DAG_MPHIDAG, 1, 0)
