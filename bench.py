@@ -176,8 +176,8 @@ def block_hop_bytes(prec, Ls, nrhs, n_in, n_out, n_extra):
     5D site of its domains once (with the F16/BF16 norms), the links of every
     output 4D site once (8 x 18 reals), and n_extra more 4D sites' worth of
     spinors for the operands read on the blocks' own sites (hop 2: M_5 p;
-    hop 4: M_5^+ y; with the snake terms the <p, A_s p> partials come from
-    hop 2's own output, so no further vector is read)."""
+    hop 4: M_5^+ y and the block residual r, which it updates in place:
+    r -= alpha A_s p; its output is r)."""
     w, n = BYTES[prec]
     site5 = (24 * w + n) * Ls * nrhs
     return (n_in + n_out + n_extra) * site5 + n_out * 144 * w
@@ -202,7 +202,7 @@ def time_block_hops(h, w, prec, nblk, reps=20, warm=3):
             e1.record(stream)
             stream.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        by = block_hop_bytes(prec, w.Ls, w.nrhs, n_in, n_out, {1: 0, 2: 1, 3: 0, 4: 1}[hop] * n_be)
+        by = block_hop_bytes(prec, w.Ls, w.nrhs, n_in, n_out, {1: 0, 2: 1, 3: 0, 4: 2}[hop] * n_be)
         fl = HOP_FLOPS_PER_SITE5 * n_out * w.Ls * w.nrhs
         out[hop] = {"us": ms * 1e3, "bytes": by, "GB/s": by / (ms * 1e-3) / 1e9,
                     "frac_hbm": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "flops": fl,

@@ -221,7 +221,9 @@ mspcg_status mspcg_debug_block_sites(mspcg_handle *h, const int nblk[4], int blo
  *   hop 2: O1 -> E2, plus M_5 applied to the block vector; with the snake
  *          terms also the per-block <p, A_s p> = |D_PC P_s p|^2 partials
  *   hop 3: E2 -> O1, daggered, M_5^{-+} M_phi^+ epilogue
- *   hop 4: O1 -> B_e, daggered, plus M_5^+ y; without the snake terms
+ *   hop 4: O1 -> B_e, daggered, plus M_5^+ y; with the snake terms it
+ *          updates the block residual in place, r -= alpha A_s p, with the
+ *          |r|^2 partials (repeated launches keep updating r); without them
  *          (pc->no_snake) it forms the <p, A_s p> partials instead
  * on the handle's block work vectors as the last preconditioner call left
  * them (zeros before any).  sites (may be NULL) receives the 4D sites of the

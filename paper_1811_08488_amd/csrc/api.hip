@@ -694,8 +694,11 @@ HopArgs block_hop_args(mspcg_handle *h, int nrhs, int nsites, const int *site_cb
 // once: 1: B_e -> O1, 2: O1 -> E2, 3: E2 -> O1, 4: O1 -> B_e (optional partial
 // Re<in, out> per workgroup).  in_mp = M_phi in (formed by the kernels that
 // write the block vector).  Returns the grid size of the launch.
+// upd_scal (last hop only): instead of storing A_s in, update the block
+// residual in place, r <- r - alpha A_s in (alpha from upd_scal per block and
+// rhs), with the partials |r|^2 of the stored values.
 int block_hop(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int which, const Vec &in, const Vec &in_mp,
-              const Vec &out, double *partial, hipStream_t st) {
+              const Vec &out, double *partial, hipStream_t st, const double *upd_scal = nullptr) {
   if (which == 1) {  // c = M_phi M_5^{-1} (-1/2 H M_phi in) on O1
     HopArgs a1 = block_hop_args(h, nrhs, bg->o1_tot, bg->d_o1_cb.as<int>(), bg->d_o1_nbr_be.as<int>(), in_mp,
                                 bg->o1v.v, 1, prec);
@@ -731,6 +734,22 @@ int block_hop(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int which, con
   a4.other_norm = bg->e2v.v.norm;
   a4.other_stride = bg->e2v.v.stride;
   a4.other_idx = bg->d_be_e2.as<int>();
+  if (upd_scal) {
+    // The update writes r in place, so the launch must not be repeated: the
+    // shape is tuned once on the same kernel writing A_s in into `out`
+    // (a scratch vector here), and the updating launch then uses it.
+    HopArgs t = a4;
+    t.partial = partial;
+    const std::vector<int> key = {4, prec, 1, 0, EPI_M5DAG_MPHIDAG, 1, 0, t.Ls, t.nrhs, t.nsites};
+    if (h->tuned.find(key) == h->tuned.end()) (void)run_hop(h, 4, prec, 1, 0, EPI_M5DAG_MPHIDAG, 1, 0, t, st);
+    a4.out = bg->r.v.data;
+    a4.out_norm = bg->r.v.norm;
+    a4.out_stride = bg->r.v.stride;
+    a4.upd_scal = upd_scal;
+    a4.upd_blk = bg->d_be_blk.as<int>();
+    a4.partial = partial;
+    return run_hop(h, 4, prec, 1, 0, EPI_M5DAG_MPHIDAG, 1, 0, a4, st, false);
+  }
   if (partial) {
     a4.partial = partial;
     a4.dotw = in.data;
@@ -805,6 +824,31 @@ void run_block_cg(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int k, dou
   const bool lazy_x = smode != 0;
   HIPCHK(block_gather(prec, ba, lazy_x ? Vec() : bg->x.v, bg->r.v, bg->p.v, bg->mp.v, r, rr, n_total, part, st));
   HIPCHK(block_scalars(2, ba, part, scal, st));
+  if (lazy_x && !bg->no_snake) {
+    // With the snake terms <p, A_s p> = |D_PC P_s p|^2 comes from the second
+    // hop, so alpha is known before the third: the last hop updates r in place
+    // (no A_s p vector, no separate r pass), and the last iteration, whose
+    // A_s p would only update r, stops after the second hop.
+    for (int it = 0; it < k; ++it) {
+      block_hop(h, bg, prec, nrhs, 1, bg->p.v, bg->mp.v, bg->Ap.v, nullptr, st);
+      BlockArgs ba2 = ba;
+      const int g2 = block_hop(h, bg, prec, nrhs, 2, bg->p.v, bg->mp.v, bg->Ap.v, part, st);
+      ba2.nsite_wg = (bg->e2_tot + g2 - 1) / g2;
+      ba2.be_off = bg->d_e2_off.as<int>();
+      HIPCHK(block_scalars(0, ba2, part, scal, st));
+      if (it + 1 == k) break;
+      block_hop(h, bg, prec, nrhs, 3, bg->p.v, bg->mp.v, bg->Ap.v, nullptr, st);
+      BlockArgs ba4 = ba;
+      const int g4 = block_hop(h, bg, prec, nrhs, 4, bg->p.v, bg->mp.v, bg->Ap.v, part, st, scal);
+      ba4.nsite_wg = (bg->be_tot + g4 - 1) / g4;
+      HIPCHK(block_scalars(1, ba4, part, scal, st));
+      HIPCHK(block_update_xp(prec, ba, bg->x.v, bg->p.v, bg->mp.v, bg->r.v, scal, it == 0, st));
+    }
+    HIPCHK(block_scatter(prec, ba, z, bg->x.v, bg->p.v, scal, smode, r, rr, n_total, partial_zr ? partial_zr : part,
+                         st));
+    if (nparts_zr) *nparts_zr = (ba.nsites + ba.nsite_wg - 1) / ba.nsite_wg;
+    return;
+  }
   if (stop) HIPCHK(inner_stop(0, bg->nb, nrhs, inner_tol, scal, stopd, st));
   for (int it = 0; it < k; ++it) {
     BlockArgs ba4 = ba;
@@ -1557,11 +1601,14 @@ mspcg_status mspcg_debug_block_hop(mspcg_handle *h, const mspcg_precond *pc, int
     ensure_links(h, prec, st);
     ensure_block_vecs(h, bg, prec, nrhs);
     double *part = bg->partial.as<double>();
-    // (the fused dot product where the solve has it: the second hop with the
-    // snake terms, the last without)
+    // (as the fixed-k solve launches them: with the snake terms the second hop
+    // forms the <p, A_s p> partials and the last updates r in place with the
+    // |r|^2 partials; without them the last forms the <p, A_s p> partials)
+    const bool upd = hop == 4 && !bg->no_snake;
     const int dot_hop = bg->no_snake ? 4 : 2;
     for (int i = 0; i < reps; ++i)
-      block_hop(h, bg, prec, nrhs, hop, bg->p.v, bg->mp.v, bg->Ap.v, hop == dot_hop ? part : nullptr, st);
+      block_hop(h, bg, prec, nrhs, hop, bg->p.v, bg->mp.v, bg->Ap.v, (hop == dot_hop || upd) ? part : nullptr, st,
+                upd ? bg->scal.as<double>() : nullptr);
     if (sites) {
       // input and output domains: 1: B_e -> O1, 2: O1 -> E2, 3: E2 -> O1, 4: O1 -> B_e
       long long nbe = 0, no1 = 0, ne2 = 0;

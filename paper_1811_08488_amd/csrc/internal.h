@@ -55,6 +55,12 @@ struct HopArgs {
   const void *mat;     // EPI_M5INV: chain coefficients of X (kChainHead + Ls values in the compute type)
   double mphi_b, mphi_c, mf, m5_alpha, m5_beta;
   double *partial;     // DOT: [gridDim.x][nrhs] partial sums of Re<w, out> (no w: |out|^2)
+  // Residual update fused into a block hop (upd_scal set): the value stored
+  // is out - alpha * hop result, out read first at the same site (in place),
+  // alpha = upd_scal[(upd_blk[site] nrhs + rhs) kScal + 1]; the DOT partials
+  // are then |stored value|^2.
+  const double *upd_scal;
+  const int *upd_blk;
   const void *dotw;
   const float *dotw_norm;
   long long dotw_stride;

@@ -694,14 +694,23 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
     pchi_add<EPI == EPI_M5DAG_MPHIDAG ? 1 : 0, XM, R>(lds, nthr, tid, s, Ls, (R)a.mf, acc, B);
   }
 
+  if (!GLOBAL && a.upd_scal && active) {  // out <- out - alpha (hop result): a fused CG residual update
+    const R al = (R)a.upd_scal[((size_t)a.upd_blk[site] * nrhs + r) * kScal + 1];
+    R ro[24];
+    load24<R>(reinterpret_cast<const S *>(a.out), a.out_norm, (size_t)r * a.out_stride + self, s, Ls, ro);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) acc[k] = fma(-al, acc[k], ro[k]);
+  }
   if (active) store24<R>(reinterpret_cast<S *>(a.out), a.out_norm, (size_t)r * a.out_stride + self, s, Ls, acc);
 
-  if (DOT) {  // Re<w, out>, or |out|^2 without w
+  if (DOT) {  // Re<w, out>, or |out|^2 without w (of the values as stored, after a fused update)
     double val = 0;
     if (active) {
       R w[24];
       if (a.dotw)
         load24<R>(reinterpret_cast<const S *>(a.dotw), a.dotw_norm, (size_t)r * a.dotw_stride + self, s, Ls, w);
+      else if (!GLOBAL && a.upd_scal)
+        stored_values<S>(acc);
       R t = 0;
 #pragma unroll
       for (int k = 0; k < 24; ++k) t += (a.dotw ? w[k] : acc[k]) * acc[k];
