@@ -306,9 +306,14 @@ HopArgs base_args(mspcg_handle *h, int nrhs) {
 // and keeps the fastest; the default shape wins ties within 3%.
 // may_tune = false (the allocation-free entry points): no timing, no events;
 // an untuned shape launches with the default and stays untuned.
+// the autotuner's key: kernel variant, list and shape
+std::vector<int> hop_key(int list_kind, int prec, int dag, int pre, int epi, int dot, int global, const HopArgs &a) {
+  return {list_kind, prec, dag, pre, epi, dot, global, a.Ls, a.nrhs, a.nsites};
+}
+
 int run_hop(mspcg_handle *h, int list_kind, int prec, int dag, int pre, int epi, int dot, int global, HopArgs a,
             hipStream_t st, bool may_tune = true) {
-  const std::vector<int> key = {list_kind, prec, dag, pre, epi, dot, global, a.Ls, a.nrhs, a.nsites};
+  const std::vector<int> key = hop_key(list_kind, prec, dag, pre, epi, dot, global, a);
   auto it = h->tuned.find(key);
   int n = 0;
   if (it != h->tuned.end()) {
@@ -740,8 +745,8 @@ int block_hop(mspcg_handle *h, BlockGeom *bg, int prec, int nrhs, int which, con
     // (a scratch vector here), and the updating launch then uses it.
     HopArgs t = a4;
     t.partial = partial;
-    const std::vector<int> key = {4, prec, 1, 0, EPI_M5DAG_MPHIDAG, 1, 0, t.Ls, t.nrhs, t.nsites};
-    if (h->tuned.find(key) == h->tuned.end()) (void)run_hop(h, 4, prec, 1, 0, EPI_M5DAG_MPHIDAG, 1, 0, t, st);
+    if (h->tuned.find(hop_key(4, prec, 1, 0, EPI_M5DAG_MPHIDAG, 1, 0, t)) == h->tuned.end())
+      (void)run_hop(h, 4, prec, 1, 0, EPI_M5DAG_MPHIDAG, 1, 0, t, st);
     a4.out = bg->r.v.data;
     a4.out_norm = bg->r.v.norm;
     a4.out_stride = bg->r.v.stride;
