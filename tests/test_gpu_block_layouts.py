@@ -58,7 +58,7 @@ def _checked_rhs(S):
     return [0, S.nrhs - 1] if S.nrhs > 1 else [0]
 
 
-@pytest.mark.parametrize("k", [1, 3])
+@pytest.mark.parametrize("k", [1, 2, 3])
 def test_local_block_cg_f64_every_layout(LY, k):
     S = LY
     r = S.rand(S.nrhs, 300 + k)
