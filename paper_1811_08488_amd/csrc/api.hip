@@ -187,7 +187,7 @@ struct mspcg_handle {
   DBuf links[4][2];
   bool links_ok[4] = {false, false, false, false};
   DBuf d_gauge;
-  // dense fifth-dimension matrices [2][Ls][Ls]
+  // fifth-dimension operators as chain coefficients (kChainHead + Ls values, F64 and F32 copies)
   Mat5 m5inv, x1;  // chain coefficients of M_5^{-1} and of M_phi M_5^{-1} (the kernels also apply the transposes)
   // FP64 workspaces
   OwnedVec tmp_o, tmp_e, tmp_o2, tmp_e2, sr, sp, sq, sz;
