@@ -280,6 +280,76 @@ template <> struct RawSite<bf16> {
   }
 };
 
+// two halves in one 32-bit register (packed half arithmetic)
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+// An operand that a kernel epilogue combines with its result, kept as stored:
+// val(k) is the stored value without the per-site norm (F16/BF16), norm()
+// that norm (1 for F64/F32).  The norm then folds into the scalar coefficient
+// that multiplies the operand, and for F16 the widening folds into a
+// mixed-precision multiply-add.
+template <typename S> struct StoredOperand {
+  using R = typename Traits<S>::R;
+  RawSite<S> raw;
+  __device__ void load(const S *base, const float *norm, size_t site4, int s, int Ls) {
+    raw.load(base, norm, site4, s, Ls);
+  }
+  __device__ R norm() const {
+    if constexpr (Traits<S>::kNorm) return raw.n;
+    else return R(1);
+  }
+  __device__ R val(int k) const {
+    if constexpr (std::is_same<S, double>::value) {
+      return (k & 1) ? raw.c[k >> 1].y : raw.c[k >> 1].x;
+    } else if constexpr (std::is_same<S, float>::value) {
+      const float4 &c = raw.c[k >> 2];
+      return (k & 3) == 0 ? c.x : (k & 3) == 1 ? c.y : (k & 3) == 2 ? c.z : c.w;
+    } else if constexpr (std::is_same<S, _Float16>::value) {
+      union { uint32_t u; _Float16 h[2]; } t;
+      t.u = raw.word(k >> 1);
+      return (float)t.h[k & 1];
+    } else {
+      const uint32_t w = raw.word(k >> 1);
+      return bf16_to_float((uint16_t)((k & 1) ? (w >> 16) : (w & 0xffffu)));
+    }
+  }
+};
+
+// store24 that also returns the sum of squares of the values as stored (what
+// a load24 would return), for norms of freshly written vectors.  F16: the
+// stored halves are squared and summed by packed dot products.
+template <typename S, typename R>
+__device__ inline R store24_sumsq(S *base, float *norm, size_t site4, int s, int Ls, R v[24]) {
+  if constexpr (std::is_same<S, _Float16>::value) {
+    float inv;
+    const float m = site_scale(v, inv);
+    norm[site4 * Ls + s] = m;
+    float t = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint32_t w[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        union { uint32_t u; _Float16 h[2]; } c;
+        c.h[0] = (_Float16)((float)v[8 * k + 2 * j] * inv);
+        c.h[1] = (_Float16)((float)v[8 * k + 2 * j + 1] * inv);
+        w[j] = c.u;
+        const half2_t h2 = __builtin_bit_cast(half2_t, c.u);
+        t = __builtin_amdgcn_fdot2(h2, h2, t, false);
+      }
+      *reinterpret_cast<uint4 *>(base + chunk_index<_Float16>(site4, s, Ls, k)) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    return t * m * m;
+  } else {
+    store24<R>(base, norm, site4, s, Ls, v);
+    stored_values<S>(v);
+    R t = 0;
+#pragma unroll
+    for (int k = 0; k < 24; ++k) t = fma(v[k], v[k], t);
+    return t;
+  }
+}
+
 // 16 bytes of link data (2 doubles, 4 floats or 8 halves) widened to the compute type.
 template <typename R> __device__ inline void widen16(const double *p, R *o) {
   const double2 t = *reinterpret_cast<const double2 *>(p);
@@ -421,7 +491,6 @@ __device__ inline void hop_half(const R h[12], const R *U, R acc[24], R n) {
 // product is exact and every sum is an FP32 sum.  The links of the workgroup
 // are staged as pairs A = (re U, -im U), B = (im U, re U) for each complex
 // entry: re(U h) = A . h and im(U h) = B . h.
-typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
 __device__ inline half2_t as_half2(uint32_t w) { return __builtin_bit_cast(half2_t, w); }
 __device__ inline half2_t times_i(half2_t z) { return half2_t{-z.y, z.x}; }

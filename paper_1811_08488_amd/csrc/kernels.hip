@@ -535,9 +535,18 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int site = tile * nsw + sl;
   const int cbr = (site < a.nsites) ? a.site_cb[site] : -1;
+  const bool has_upd = !GLOBAL && a.upd_scal;
+  const int ublk = (has_upd && site < a.nsites) ? a.upd_blk[site] : -1;
   const bool active = lane_ok && cbr >= 0;
   const int cb = active ? cbr : 0;
   const int self = GLOBAL ? cb : site;  // index of this site in tables and outputs
+  // A fused CG residual update (block domains, upd_scal set) stores
+  // out - alpha (result): alpha is requested here, long before it is needed,
+  // and -alpha folds into the epilogue's coefficients (all linear in the
+  // result).
+  const bool upd = has_upd && active;
+  double alpha_u = 0;
+  if (upd) alpha_u = a.upd_scal[((size_t)ublk * nrhs + r) * kScal + 1];
 
   // The eight neighbour indices are loaded once, with two 16-byte loads, and
   // kept in registers (rotated by two per direction pair below): no spinor
@@ -663,6 +672,9 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
   }
 
   const R scale = (R)(PRE ? a.scale * a.mphi_b : a.scale);
+  // (the opaque copy keeps the conversion, and so the wait for the load, here)
+  asm volatile("" : "+v"(alpha_u));
+  const R fu = upd ? -(R)alpha_u : R(1);
   if (EPI == EPI_M5INV) {
     m5_chain<DAG, R>(lds, tid, s, Ls, G, reinterpret_cast<const R *>(a.mat), scale, acc);
   } else if (EPI == EPI_MPHIDAG) {
@@ -674,46 +686,64 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
     for (int k = 0; k < 24; ++k) acc[k] *= scale;
   }
   if (EPI == EPI_M5_OTHER || EPI == EPI_M5DAG_MPHIDAG) {
-    int oi = GLOBAL ? cb : (active ? (a.other_idx ? a.other_idx[site] : site) : -1);
-    R o[24];
-    zero24(o);
-    if (oi >= 0)  // (outside the block domain the operand vanishes)
-      load24<R>(reinterpret_cast<const S *>(a.other), a.other_norm, (size_t)r * a.other_stride + oi, s, Ls, o);
+    // (outside the block domain the operand vanishes: it is read at index 0
+    // and enters with weight zero)
+    const int oi = GLOBAL ? cb : (active ? (a.other_idx ? a.other_idx[site] : site) : -1);
+    StoredOperand<S> o;
+    o.load(reinterpret_cast<const S *>(a.other), a.other_norm, (size_t)r * a.other_stride + (oi >= 0 ? oi : 0), s,
+           Ls);
+    const R ow = oi >= 0 ? o.norm() * fu : R(0);
     // M_5 = alpha - beta P_chi, M_5^+ = alpha - beta P_chi^+, M_phi^+ = b + c P_chi^+:
     //   M_5 o + scale h                 = (alpha o + scale h) + P_chi (-beta o)
     //   M_5^+ o + scale M_phi^+ h       = (alpha o + scale b h) + P_chi^+ (-beta o + scale c h)
-    const R al = (R)a.m5_alpha, mbe = (R)(-a.m5_beta);
-    const R sb = EPI == EPI_M5DAG_MPHIDAG ? scale * (R)a.mphi_b : scale;
-    const R sc = EPI == EPI_M5DAG_MPHIDAG ? scale * (R)a.mphi_c : R(0);
+    // (every coefficient times fu; the operand's norm with those of o)
+    const R al = (R)a.m5_alpha * ow, mbe = (R)(-a.m5_beta) * ow;
+    const R sb = (EPI == EPI_M5DAG_MPHIDAG ? scale * (R)a.mphi_b : scale) * fu;
+    const R sc = (R)a.mphi_c * scale * fu;
     R B[24];
 #pragma unroll
     for (int k = 0; k < 24; ++k) {
-      B[k] = fma(sc, acc[k], mbe * o[k]);
-      acc[k] = fma(sb, acc[k], al * o[k]);
+      const R ok = o.val(k);
+      B[k] = EPI == EPI_M5DAG_MPHIDAG ? fma(ok, mbe, sc * acc[k]) : ok * mbe;
+      acc[k] = fma(ok, al, sb * acc[k]);
     }
     pchi_add<EPI == EPI_M5DAG_MPHIDAG ? 1 : 0, XM, R>(lds, nthr, tid, s, Ls, (R)a.mf, acc, B);
+  } else if (upd) {
+#pragma unroll
+    for (int k = 0; k < 24; ++k) acc[k] *= fu;
   }
 
-  if (!GLOBAL && a.upd_scal && active) {  // out <- out - alpha (hop result): a fused CG residual update
-    const R al = (R)a.upd_scal[((size_t)a.upd_blk[site] * nrhs + r) * kScal + 1];
-    R ro[24];
-    load24<R>(reinterpret_cast<const S *>(a.out), a.out_norm, (size_t)r * a.out_stride + self, s, Ls, ro);
+  R sumsq = 0;  // |out|^2 of the values as stored (DOT after a fused update)
+  if (upd) {  // out <- out - alpha (result), read in place
+    StoredOperand<S> ro;
+    ro.load(reinterpret_cast<const S *>(a.out), a.out_norm, (size_t)r * a.out_stride + self, s, Ls);
+    const R rn = ro.norm();
 #pragma unroll
-    for (int k = 0; k < 24; ++k) acc[k] = fma(-al, acc[k], ro[k]);
+    for (int k = 0; k < 24; ++k) acc[k] = fma(ro.val(k), rn, acc[k]);
+    if (DOT && !a.dotw)
+      sumsq = store24_sumsq<S, R>(reinterpret_cast<S *>(a.out), a.out_norm, (size_t)r * a.out_stride + self, s, Ls,
+                                  acc);
+    else
+      store24<R>(reinterpret_cast<S *>(a.out), a.out_norm, (size_t)r * a.out_stride + self, s, Ls, acc);
+  } else if (active) {
+    store24<R>(reinterpret_cast<S *>(a.out), a.out_norm, (size_t)r * a.out_stride + self, s, Ls, acc);
   }
-  if (active) store24<R>(reinterpret_cast<S *>(a.out), a.out_norm, (size_t)r * a.out_stride + self, s, Ls, acc);
 
   if (DOT) {  // Re<w, out>, or |out|^2 without w (of the values as stored, after a fused update)
     double val = 0;
     if (active) {
-      R w[24];
-      if (a.dotw)
-        load24<R>(reinterpret_cast<const S *>(a.dotw), a.dotw_norm, (size_t)r * a.dotw_stride + self, s, Ls, w);
-      else if (!GLOBAL && a.upd_scal)
-        stored_values<S>(acc);
       R t = 0;
+      if (a.dotw) {
+        R w[24];
+        load24<R>(reinterpret_cast<const S *>(a.dotw), a.dotw_norm, (size_t)r * a.dotw_stride + self, s, Ls, w);
 #pragma unroll
-      for (int k = 0; k < 24; ++k) t += (a.dotw ? w[k] : acc[k]) * acc[k];
+        for (int k = 0; k < 24; ++k) t += w[k] * acc[k];
+      } else if (upd) {
+        t = sumsq;
+      } else {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) t += acc[k] * acc[k];
+      }
       val = (double)t;
     }
     wg_partial(reinterpret_cast<double *>(smem), nthr, tid, Ls, nrhs, nsw, G, val, a.partial, tile);
