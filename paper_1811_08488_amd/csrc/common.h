@@ -294,6 +294,7 @@ template <typename S> struct StoredOperand {
   __device__ void load(const S *base, const float *norm, size_t site4, int s, int Ls) {
     raw.load(base, norm, site4, s, Ls);
   }
+  __device__ void zero() { raw = RawSite<S>{}; }
   __device__ R norm() const {
     if constexpr (Traits<S>::kNorm) return raw.n;
     else return R(1);

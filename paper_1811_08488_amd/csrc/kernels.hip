@@ -686,12 +686,13 @@ __global__ void __launch_bounds__(256, (HopWaves<S, XM>::value)) hop_kernel(cons
     for (int k = 0; k < 24; ++k) acc[k] *= scale;
   }
   if (EPI == EPI_M5_OTHER || EPI == EPI_M5DAG_MPHIDAG) {
-    // (outside the block domain the operand vanishes: it is read at index 0
-    // and enters with weight zero)
+    // (outside the block domain the operand vanishes; those lanes load
+    // nothing: a shared substitute site would draw the reads of every such
+    // lane onto one cache line)
     const int oi = GLOBAL ? cb : (active ? (a.other_idx ? a.other_idx[site] : site) : -1);
     StoredOperand<S> o;
-    o.load(reinterpret_cast<const S *>(a.other), a.other_norm, (size_t)r * a.other_stride + (oi >= 0 ? oi : 0), s,
-           Ls);
+    o.zero();
+    if (oi >= 0) o.load(reinterpret_cast<const S *>(a.other), a.other_norm, (size_t)r * a.other_stride + oi, s, Ls);
     const R ow = oi >= 0 ? o.norm() * fu : R(0);
     // M_5 = alpha - beta P_chi, M_5^+ = alpha - beta P_chi^+, M_phi^+ = b + c P_chi^+:
     //   M_5 o + scale h                 = (alpha o + scale h) + P_chi (-beta o)
