@@ -7,10 +7,12 @@ residual of 1e-10, on a seeded synthetic gauge field and source that are
 resident in HBM before timing starts.
 
 The default workload is Moebius 24^3x64 x Ls=24 (2x2x2x4 blocks of 12^3x16,
-8 inner FP16 iterations): far larger than the 256 MB last-level cache, and a
-20-step run with 5 warm-up solves fits in a few minutes.  The largest one-GPU
-workload (48^3x96 x 12) takes about a minute per solve; run it with
---workload mobius_48x48x48x96_ls12 and fewer steps.
+8 inner FP16 iterations): far larger than the 256 MB last-level cache, and
+the default run (one warm-up and three timed solves, plain CG, one more
+MSPCG solve at 4 inner iterations, the kernel timings and the CPU baseline)
+takes about four minutes.  The largest one-GPU workload (48^3x96 x 12) takes
+about 40 s per solve; run it with --workload mobius_48x48x48x96_ls12 and
+--steps 1.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
     python bench.py --workload NAME --oracle-check    # full FP64 CPU oracle solve next to the GPU's
