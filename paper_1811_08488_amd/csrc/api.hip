@@ -1233,9 +1233,9 @@ mspcg_status mspcg_create(mspcg_handle **hp, const mspcg_dwf *p, const double *g
     const int *L = p->L;
     const int Lxh = L[0] / 2;
     // output sites of the full-lattice hop are visited column by column: the
-    // lattice is cut into columns of 8x8x8 spatial sites (the full extent where
-    // 8 does not divide it) running the whole time direction, and each column
-    // is swept along t.  Consecutive workgroups (one XCD each range, see the
+    // lattice is cut into columns of 12x12x12 spatial sites (8 where 12 does
+    // not divide an extent, the full extent where neither does) running the
+    // whole time direction, and each column is swept along t.  Consecutive workgroups (one XCD each range, see the
     // kernels' workgroup renumbering) then need only a few neighbouring time
     // slices of one column at a time, which stay in that XCD's L2.
     int cdim[3];
